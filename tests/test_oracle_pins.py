@@ -1,0 +1,270 @@
+"""Pins of the CPU oracle against values the paper and the mathematics fix.
+
+Nothing here compares the oracle with itself: each check uses printed values,
+closed forms, invariants, library routines or arbitrary-precision brute force.
+"""
+from __future__ import annotations
+
+import math
+import os
+
+import mpmath as mp
+import numpy as np
+import pytest
+
+from paper_2510_05282_amd import workloads
+from tests import appc_forms
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+LD = np.longdouble
+PI_LD = LD("3.14159265358979323846264338327950288")
+
+
+def _row(l, m):
+    return l * l + l + m
+
+
+def _mpf(v):
+    """Exact conversion of a long double to mpmath (as a sum of two doubles)."""
+    hi = float(v)
+    lo = float(LD(v) - LD(hi))
+    return mp.mpf(hi) + mp.mpf(lo)
+
+
+def _load_table(name):
+    vals = {}
+    for ln in open(os.path.join(GOLDEN, name)):
+        ln = ln.strip()
+        if not ln or ln.startswith("#"):
+            continue
+        parts = ln.split()
+        l, m = int(parts[0]), int(parts[1])
+        vals[(l, m)] = [float(v) for v in parts[2:]]
+    return vals
+
+
+# Appendix D: points of Tables ref1 and ref2 (the second with the decimal point of
+# phi restored, see tests/golden/appD_table_ref2.txt)
+APPD = {
+    "appD_table_ref1.txt": ("2.12160245947564796", "-1.82732370250979703"),
+    "appD_table_ref2.txt": ("1.69050041976591414", "0.758228122208986166"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(APPD))
+def test_appendix_d_reference_values(orc, name):
+    """Appendix D tables: 2 x 100 printed FP64 values (reading: first value column
+    is R_l^{+m}, second is R_l^{-m})."""
+    th, ph = APPD[name]
+    Y = orc.eval_angles(9, [LD(th)], [LD(ph)])[:, 0]
+    vals = _load_table(name)
+    assert len(vals) == 55
+    worst = 0.0
+    for (l, m), v in vals.items():
+        if m == 0:
+            worst = max(worst, abs(float(Y[_row(l, 0)]) - v[0]))
+        else:
+            worst = max(worst, abs(float(Y[_row(l, m)]) - v[0]))
+            worst = max(worst, abs(float(Y[_row(l, -m)]) - v[1]))
+    assert worst <= 1e-15, worst
+
+
+def test_appendix_d_readings_are_needed(orc):
+    """The columns as labelled, or phi as printed in Table ref2, do not match."""
+    vals = _load_table("appD_table_ref1.txt")
+    Y = orc.eval_angles(9, [LD(APPD["appD_table_ref1.txt"][0])],
+                        [LD(APPD["appD_table_ref1.txt"][1])])[:, 0]
+    as_labelled = max(abs(float(Y[_row(l, -m)]) - v[0]) for (l, m), v in vals.items() if m > 0)
+    assert as_labelled > 0.1
+    vals2 = _load_table("appD_table_ref2.txt")
+    Y2 = orc.eval_angles(9, [LD("1.69050041976591414")], [LD("7.58228122208986166")])[:, 0]
+    printed_phi = max(abs(float(Y2[_row(l, m)]) - v[0]) for (l, m), v in vals2.items())
+    assert printed_phi > 0.1
+
+
+def _mp_real_ylm(l, m, theta, phi):
+    """Real harmonic from the complex one (mpmath.spherharm, which carries the
+    Condon-Shortley phase) by the paper's eq. real_harmomics, literally."""
+    if m == 0:
+        return mp.re(mp.spherharm(l, 0, theta, phi))
+    if m < 0:
+        v = 1j / mp.sqrt(2) * (mp.spherharm(l, m, theta, phi)
+                               - (-1) ** m * mp.spherharm(l, -m, theta, phi))
+    else:
+        v = 1 / mp.sqrt(2) * (mp.spherharm(l, -m, theta, phi)
+                              + (-1) ** m * mp.spherharm(l, m, theta, phi))
+    assert abs(mp.im(v)) < mp.mpf(10) ** (-30)
+    return mp.re(v)
+
+
+def _mp_angles(x, y, z):
+    r = mp.sqrt(x * x + y * y + z * z)
+    return mp.acos(z / r), mp.atan2(y, x)
+
+
+def test_definition_brute_force_mpmath(orc):
+    """Cartesian oracle vs eq. real_harmomics over mpmath's complex Y at 40 digits,
+    on random points and points close to the poles and axes."""
+    mp.mp.dps = 40
+    pts = np.concatenate([workloads.isotropic_points(24, 0.1, 5.0, seed=7),
+                          np.array([[1e-7, 2e-7, 1.0], [3e-9, -1e-9, -2.0], [1.0, 0.0, 0.0],
+                                    [0.0, -3.0, 0.0], [0.5, 0.5, 1e-12], [-2.0, 1.0, -0.5]])])
+    Y = orc.eval_xyz(9, pts)
+    worst = 0.0
+    for i, (x, y, z) in enumerate(pts):
+        th, ph = _mp_angles(mp.mpf(x), mp.mpf(y), mp.mpf(z))
+        for l in range(10):
+            for m in range(-l, l + 1):
+                ref = _mp_real_ylm(l, m, th, ph)
+                worst = max(worst, abs(float(_mpf(Y[_row(l, m), i]) - ref)))
+    assert worst <= 2e-17, worst
+
+
+def test_library_routine_scipy(orc):
+    """scipy.special.sph_harm_y (complex, Condon-Shortley phase) through
+    eq. real_harmomics, in double precision."""
+    from scipy.special import sph_harm_y
+    pts = workloads.isotropic_points(500, 0.1, 5.0, seed=3)
+    x, y, z = pts.T
+    th = np.arccos(z / np.sqrt((pts * pts).sum(1)))
+    ph = np.arctan2(y, x)
+    Y = orc.eval_xyz(9, pts).astype(np.float64)
+    for l in range(10):
+        for m in range(-l, l + 1):
+            if m == 0:
+                ref = sph_harm_y(l, 0, th, ph).real
+            elif m < 0:
+                ref = (1j / math.sqrt(2) * (sph_harm_y(l, m, th, ph)
+                                            - (-1) ** m * sph_harm_y(l, -m, th, ph))).real
+            else:
+                ref = (1 / math.sqrt(2) * (sph_harm_y(l, -m, th, ph)
+                                           + (-1) ** m * sph_harm_y(l, m, th, ph))).real
+            assert np.abs(Y[_row(l, m)] - ref).max() <= 5e-14, (l, m)
+
+
+def test_appendix_c_forms_match_definition(orc):
+    """Every Appendix C formula (with the three corrected readings), and every m>0
+    value from Appendix B rotations, against the oracle at 40-digit precision."""
+    mp.mp.dps = 40
+    F = appc_forms.forms()
+    pts = workloads.isotropic_points(30, 0.5, 2.0, seed=11)
+    Y = orc.eval_xyz(9, pts)
+    for i, (x, y, z) in enumerate(pts):
+        X, Yv, Z = mp.mpf(x), mp.mpf(y), mp.mpf(z)
+        r = mp.sqrt(X * X + Yv * Yv + Z * Z)
+        xb, yb, zb = X / r, Yv / r, Z / r
+        for key, f in F.items():
+            if len(key) == 3 and key[2] == "printed":
+                continue
+            l, m = key[0], key[1]
+            err = abs(f(xb, yb, zb) - _mpf(Y[_row(l, m), i]))
+            assert err <= 2e-17, (key, float(err))
+        for l in range(1, 10):
+            for m in range(1, l + 1):
+                v = appc_forms.positive_m(l, m, xb, yb, zb)
+                err = abs(v - _mpf(Y[_row(l, m), i]))
+                assert err <= 2e-17, ((l, m), float(err))
+
+
+def test_appendix_c_garbled_forms_are_garbled(orc):
+    """The three printed forms that the corrected readings replace are wrong."""
+    mp.mp.dps = 40
+    F = appc_forms.forms()
+    pts = workloads.isotropic_points(5, 0.5, 2.0, seed=12)
+    Y = orc.eval_xyz(9, pts)
+    for key in [(5, 0, "printed"), (8, -1, "printed"), (9, -7, "printed")]:
+        errs = []
+        for i, (x, y, z) in enumerate(pts):
+            X, Yv, Z = mp.mpf(x), mp.mpf(y), mp.mpf(z)
+            r = mp.sqrt(X * X + Yv * Yv + Z * Z)
+            errs.append(abs(F[key](X / r, Yv / r, Z / r) - _mpf(Y[_row(key[0], key[1]), i])))
+        assert max(errs) > 1e-3, key
+
+
+def test_poles_and_origin(orc):
+    """At +-z only m = 0 survives: R_l^0(+-z) = (+-1)^l sqrt((2l+1)/(4 pi)).
+    At r = 0 only l = 0 is nonzero (paper, Section 2)."""
+    pts = np.array([[0, 0, 2.5], [0, 0, -0.1], [0, 0, 1e-200], [0, 0, 0.0]], dtype=np.float64)
+    Y = orc.eval_xyz(9, pts)
+    for l in range(10):
+        for m in range(-l, l + 1):
+            for i, sgn in enumerate([1, -1, 1]):
+                ref = sgn ** l * np.sqrt(LD(2 * l + 1) / (4 * PI_LD)) if m == 0 else LD(0)
+                assert abs(Y[_row(l, m), i] - ref) <= 1e-18
+            ref0 = 1 / np.sqrt(4 * PI_LD) if l == 0 else LD(0)
+            assert abs(Y[_row(l, m), 3] - ref0) <= 1e-19
+
+
+def _dfact(n):
+    return 1 if n <= 0 else n * _dfact(n - 2)
+
+
+def test_equator_axes_closed_form(orc):
+    """On the +-x and +-y axes: P~_l^m(0) = 0 for odd l+m, else
+    (-1)^((l-m)/2) (l+m-1)!!/(l-m)!!, and cos(m phi), sin(m phi) in {0, +-1}."""
+    axes = {(1, 0, 0): 0.0, (0, 1, 0): math.pi / 2, (-1, 0, 0): math.pi, (0, -1, 0): -math.pi / 2}
+    pts = np.array([[3 * a for a in k] for k in axes], dtype=np.float64)
+    Y = orc.eval_xyz(9, pts)
+    for i, phi in enumerate(axes.values()):
+        for l in range(10):
+            for m in range(0, l + 1):
+                P = 0.0 if (l + m) % 2 else (-1) ** ((l - m) // 2) * _dfact(l + m - 1) / _dfact(l - m)
+                N = np.sqrt(LD(2 * l + 1) / (4 * PI_LD) * LD(math.factorial(l - m))
+                            / LD(math.factorial(l + m)))
+                c = round(math.cos(m * phi))
+                s = round(math.sin(m * phi))
+                if m == 0:
+                    assert abs(Y[_row(l, 0), i] - N * P) <= 1e-18
+                else:
+                    assert abs(Y[_row(l, m), i] - np.sqrt(LD(2)) * N * P * c) <= 1e-18
+                    assert abs(Y[_row(l, -m), i] - np.sqrt(LD(2)) * N * P * s) <= 1e-18
+
+
+def test_addition_theorem(orc):
+    """sum_m (R_l^m)^2 = (2l+1)/(4 pi) for every l and every direction."""
+    sp = workloads.special_points()
+    pts = np.concatenate([workloads.isotropic_points(2000, 0.01, 10, seed=5),
+                          sp[(sp * sp).sum(1) > 0]])
+    Y = orc.eval_xyz(9, pts)
+    for l in range(10):
+        s = (Y[l * l:(l + 1) * (l + 1)] ** 2).sum(axis=0)
+        ref = LD(2 * l + 1) / (4 * PI_LD)
+        assert (np.abs(s - ref) / ref).max() <= 1e-17
+
+
+def test_orthonormality_exact_quadrature(orc):
+    """Gauss-Legendre (10 nodes in cos theta) x 19 uniform phi integrates every
+    product R_l^m R_l'^m' with l, l' <= 9 exactly; the Gram matrix is I."""
+    xg, wg = np.polynomial.legendre.leggauss(10)
+    nphi = 19
+    phis = 2 * np.pi * np.arange(nphi) / nphi
+    th = np.repeat(np.arccos(xg), nphi)
+    ph = np.tile(phis, 10)
+    w = np.repeat(wg, nphi) * (2 * np.pi / nphi)
+    Y = orc.eval_angles(9, th.astype(LD), ph.astype(LD)).astype(np.float64)
+    G = (Y * w) @ Y.T
+    assert np.abs(G - np.eye(100)).max() <= 1e-14
+
+
+def test_parity_and_mirror(orc):
+    """R(-u) = (-1)^l R(u); y -> -y flips the sign of m < 0 terms only."""
+    pts = workloads.isotropic_points(300, 0.1, 5, seed=9)
+    Y = orc.eval_xyz(9, pts)
+    Yn = orc.eval_xyz(9, -pts)
+    mirror = pts * np.array([1, -1, 1])
+    Ym = orc.eval_xyz(9, mirror)
+    for l in range(10):
+        for m in range(-l, l + 1):
+            assert np.abs(Yn[_row(l, m)] - (-1) ** l * Y[_row(l, m)]).max() <= 1e-17
+            sgn = -1 if m < 0 else 1
+            assert np.abs(Ym[_row(l, m)] - sgn * Y[_row(l, m)]).max() <= 1e-17
+
+
+def test_scale_invariance_and_f32_widening(orc):
+    """Only the direction matters; float32 inputs are widened exactly."""
+    pts = workloads.isotropic_points(200, 0.1, 5, seed=4)
+    Y1 = orc.eval_xyz(9, pts)
+    Y2 = orc.eval_xyz(9, pts * 1024.0)
+    assert np.abs(Y1 - Y2).max() <= 1e-17
+    p32 = pts.astype(np.float32)
+    assert np.array_equal(orc.eval_xyz(9, p32), orc.eval_xyz(9, p32.astype(np.float64)))
