@@ -54,8 +54,14 @@ def lib():
         L.orc_spline_setup.argtypes = [i32, ctypes.c_double, vp, vp]
         L.orc_spline_eval.argtypes = [i32, ctypes.c_double, vp, vp, i64, vp, vp]
         L.orc_projectors.argtypes = [i32, i32, vp, vp, vp, vp, i32, ctypes.c_double, vp, vp, vp]
+        L.orc_num_threads.restype = i32
         _lib = L
     return _lib
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle's batch loops use."""
+    return int(lib().orc_num_threads())
 
 
 def _p(a: np.ndarray):

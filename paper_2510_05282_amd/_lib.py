@@ -1,0 +1,57 @@
+"""Loader of libshmi.so (ctypes).
+
+torch is imported first on purpose: it loads its own HIP runtime
+(libamdhip64.so.7), and the dynamic linker then binds libshmi.so to that same
+runtime, so device pointers and stream handles from torch are valid in the
+library.  There is no fallback: without the built library every call fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # noqa: F401  (must precede the CDLL load, see above)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libshmi.so")
+
+_lib = None
+
+
+class ShError(RuntimeError):
+    """A libshmi call returned a nonzero status."""
+
+    def __init__(self, fn: str, code: int, hip: int = 0):
+        self.code = code
+        self.hip = hip
+        msg = f"{fn} failed: {lib().sh_strerror(code).decode()} (status {code})"
+        if hip:
+            msg += f", hipError {hip}"
+        super().__init__(msg)
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2510_05282_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    i32, i64, vp = ctypes.c_int, ctypes.c_int64, ctypes.c_void_p
+    L.sh_eval.argtypes = [i32, i64, vp, vp, vp]
+    L.sh_eval.restype = i32
+    L.sh_eval_f32.argtypes = [i32, i64, vp, vp, vp]
+    L.sh_eval_f32.restype = i32
+    L.sh_eval_ld.argtypes = [i32, i64, vp, vp, i64, i32, vp]
+    L.sh_eval_ld.restype = i32
+    L.sh_strerror.argtypes = [i32]
+    L.sh_strerror.restype = ctypes.c_char_p
+    L.sh_last_hip_error.argtypes = []
+    L.sh_last_hip_error.restype = i32
+    _lib = L
+    return _lib
+
+
+def check(fn: str, rc: int) -> None:
+    if rc != 0:
+        raise ShError(fn, rc, lib().sh_last_hip_error() if rc == 2 else 0)

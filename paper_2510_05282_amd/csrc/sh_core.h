@@ -1,0 +1,171 @@
+// sh_core.h -- the per-point formula core shared by the GPU kernels.
+//
+// Real spherical harmonics R_l^m, l <= 9, on a unit vector (x, y, z), from the
+// paper's explicit factorised Cartesian formulas (Appendix C for m <= 0,
+// Appendix B for m > 0), using only adds and multiplies and the pair factor
+// p(a, b) = (a - b)(a + b) (eq. rpair).  Each value is
+//     R_l^-m = kA[l][m] * Z_lm(z) * Shat_m(x, y),   R_l^+m = kB[l][m] * Z_lm(z) * Chat_m(x, y)
+// (sh_constants.h documents the three factors).  Z_lm is shared by +m and -m,
+// so each z-polynomial is evaluated once per point rather than once per sign of m.
+//
+// Row of (l, m) in every output: l*l + l + m.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "sh_constants.h"
+
+namespace shk {
+
+constexpr int row(int l, int m) { return l * l + l + m; }
+constexpr int nfun(int lmax) { return (lmax + 1) * (lmax + 1); }
+
+template <int B, int E, typename F>
+__host__ __device__ __forceinline__ void static_for(F&& f)
+{
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+// Constants in the arithmetic type of the polynomials.
+template <typename T> struct K;
+template <> struct K<double> {
+    static __host__ __device__ constexpr double zroot(int l, int m, int k) { return shc::kZRoot[l][m][k]; }
+    static __host__ __device__ constexpr double a(int l, int m) { return shc::kA[l][m]; }
+    static __host__ __device__ constexpr double b(int l, int m) { return shc::kB[l][m]; }
+    static __host__ __device__ constexpr double tans(int m, int k) { return shc::kTanS[m][k]; }
+    static __host__ __device__ constexpr double tanc(int m, int k) { return shc::kTanC[m][k]; }
+};
+template <> struct K<float> {
+    static __host__ __device__ constexpr float zroot(int l, int m, int k) { return shc::kZRootF[l][m][k]; }
+    static __host__ __device__ constexpr float a(int l, int m) { return shc::kAF[l][m]; }
+    static __host__ __device__ constexpr float b(int l, int m) { return shc::kBF[l][m]; }
+    static __host__ __device__ constexpr float tans(int m, int k) { return shc::kTanSF[m][k]; }
+    static __host__ __device__ constexpr float tanc(int m, int k) { return shc::kTanCF[m][k]; }
+};
+
+// Pair factor p(a, b) = (a - b)(a + b), eq. rpair: kept as a product of the two
+// root factors rather than a^2 - b^2.
+template <typename T>
+__host__ __device__ __forceinline__ T pf(T a, T b) { return (a - b) * (a + b); }
+
+// Shat_m(x, y) = y * x^[m even] * prod_{k=1}^{ceil(m/2)-1} p(tan(k pi/m) x, y).
+template <typename T, int M>
+__host__ __device__ __forceinline__ T shat(T x, T y)
+{
+    T acc = y;
+    if constexpr (M % 2 == 0) acc *= x;
+    static_for<0, (M + 1) / 2 - 1>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        acc *= pf(K<T>::tans(M, k) * x, y);
+    });
+    return acc;
+}
+
+// Chat_m(x, y) = x^[m odd] * prod_{k=0}^{floor(m/2)-1} p(tan((k+1/2) pi/m) x, y).
+template <typename T, int M>
+__host__ __device__ __forceinline__ T chat(T x, T y)
+{
+    T acc;
+    if constexpr (M % 2 == 1) acc = x;
+    static_for<0, M / 2>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        const T f = pf(K<T>::tanc(M, k) * x, y);
+        if constexpr (k == 0 && M % 2 == 0) acc = f;
+        else acc *= f;
+    });
+    return acc;
+}
+
+// Z_lm(z) = z^((l-m) mod 2) * prod_k p(r_k, z), r_k the positive roots of d^m P_l/dz^m.
+template <typename T, int L, int M>
+__host__ __device__ __forceinline__ T zfac(T z)
+{
+    constexpr int np = (L - M) / 2;
+    constexpr bool odd = ((L - M) & 1) != 0;
+    if constexpr (np == 0) {
+        if constexpr (odd) return z;
+        else return T(1);
+    } else {
+        T acc = pf(K<T>::zroot(L, M, 0), z);
+        static_for<1, np>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            acc *= pf(K<T>::zroot(L, M, k), z);
+        });
+        if constexpr (odd) acc *= z;
+        return acc;
+    }
+}
+
+// All (LMAX+1)^2 values at the unit vector (x, y, z); sink(row, value) receives
+// each one, m-major (so each xy factor is live only while its m is processed).
+// `keep` multiplies the rows that are nonzero at x = y = z = 0 besides l = 0
+// (even l > 0, m = 0): 1 normally, 0 at the origin, where only l = 0 survives
+// (paper, Section 2).
+template <int LMAX, typename T, typename Sink>
+__host__ __device__ __forceinline__ void eval_unit(T x, T y, T z, T keep, Sink&& sink)
+{
+    static_assert(LMAX >= 0 && LMAX <= shc::kLmax, "lmax out of range");
+    static_for<0, LMAX + 1>([&](auto mc) {
+        constexpr int M = decltype(mc)::value;
+        if constexpr (M == 0) {
+            static_for<0, LMAX + 1>([&](auto lc) {
+                constexpr int L = decltype(lc)::value;
+                T v = K<T>::a(L, 0) * zfac<T, L, 0>(z);
+                if constexpr (L > 0 && L % 2 == 0) v *= keep;
+                sink(row(L, 0), v);
+            });
+        } else {
+            const T s = shat<T, M>(x, y);
+            const T c = chat<T, M>(x, y);
+            static_for<M, LMAX + 1>([&](auto lc) {
+                constexpr int L = decltype(lc)::value;
+                const T zf = zfac<T, L, M>(z);
+                sink(row(L, -M), K<T>::a(L, M) * zf * s);
+                sink(row(L, M), K<T>::b(L, M) * zf * c);
+            });
+        }
+    });
+}
+
+// 1/sqrt(a) for a > 0: the hardware estimate (v_rsq_f64) refined by two Newton
+// steps y <- y + y (1 - a y^2) / 2, each evaluated with fused multiply-adds.
+__device__ __forceinline__ double rsqrt_refined(double a)
+{
+    double y = __builtin_amdgcn_rsq(a);
+    double e = __builtin_fma(-(a * y), y, 1.0);
+    y = __builtin_fma(0.5 * y, e, y);
+    e = __builtin_fma(-(a * y), y, 1.0);
+    y = __builtin_fma(0.5 * y, e, y);
+    return y;
+}
+
+// Unit vector of (x, y, z) in double, with the near-origin guard: coordinates
+// whose squares would underflow (or overflow) are first scaled by an exact power
+// of two, which leaves the direction unchanged.  At exactly r = 0 the unit vector
+// is returned as 0 and keep = 0.  NaN propagates.
+__device__ __forceinline__ void normalize(double x, double y, double z,
+                                          double& xb, double& yb, double& zb, double& keep)
+{
+    const double mx = fmax(fabs(x), fmax(fabs(y), fabs(z)));
+    if (mx < 0x1p-500 || mx > 0x1p+500) {
+        const double s = mx < 0x1p-500 ? 0x1p+600 : 0x1p-600;
+        x *= s;
+        y *= s;
+        z *= s;
+    }
+    const double r2 = __builtin_fma(x, x, __builtin_fma(y, y, z * z));
+    const bool nz = r2 > 0.0;
+    const double ri = nz ? rsqrt_refined(r2) : 0.0;
+    xb = x * ri;
+    yb = y * ri;
+    zb = z * ri;
+    keep = nz ? 1.0 : 0.0;
+}
+
+}  // namespace shk

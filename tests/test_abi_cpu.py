@@ -1,0 +1,55 @@
+"""The C ABI on the CPU: the library loads, exports every function include/shmi.h
+declares, and rejects bad arguments before any HIP call (no GPU needed)."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "shmi.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b(sh_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2510_05282_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libshmi.so is not built (run `python -m paper_2510_05282_amd.build`)")
+    return _lib.lib()
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = _declared()
+    assert "sh_eval" in names and "sh_strerror" in names
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_strerror(L):
+    assert L.sh_strerror(0) == b"success"
+    assert L.sh_strerror(1) == b"invalid argument"
+    assert L.sh_strerror(12345) == b"unknown status code"
+
+
+def test_eval_argument_validation(L):
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: every call below is rejected first
+    assert L.sh_eval(10, 5, fake, fake, None) == 1
+    assert L.sh_eval(-1, 5, fake, fake, None) == 1
+    assert L.sh_eval(3, -1, fake, fake, None) == 1
+    assert L.sh_eval(3, 5, None, fake, None) == 1
+    assert L.sh_eval(3, 5, fake, None, None) == 1
+    assert L.sh_eval_f32(3, 5, None, fake, None) == 1
+    assert L.sh_eval_ld(3, 5, fake, fake, 4, 0, None) == 1  # ld < n
+    assert L.sh_eval_ld(3, 5, fake, fake, 5, 7, None) == 1  # bad dtype
+    # n == 0 is a no-op, even with NULL pointers
+    assert L.sh_eval(9, 0, None, None, None) == 0
+    assert L.sh_eval_f32(0, 0, None, None, None) == 0

@@ -1,0 +1,192 @@
+"""GPU parity of sh_eval / sh_eval_f32 / sh_eval_ld against the CPU oracle.
+
+Tolerances: max abs error 1e-13 in FP64 and 5e-6 in FP32 (the FP32 oracle runs
+at the float inputs, widened exactly)."""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2510_05282_amd as sh
+from paper_2510_05282_amd import workloads
+
+pytestmark = pytest.mark.gpu
+LD = np.longdouble
+TOL64 = 1e-13
+TOL32 = 5e-6
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _per_l(err_rows, lmax):
+    return ["%.1e" % float(err_rows[l * l:(l + 1) ** 2].max()) for l in range(lmax + 1)]
+
+
+def _gpu(dev, lmax, pts, dtype=torch.float64):
+    x = torch.from_numpy(np.ascontiguousarray(pts)).to(dev, dtype)
+    fn = sh.sh_eval if dtype == torch.float64 else sh.sh_eval_f32
+    y = fn(lmax, x)
+    torch.cuda.synchronize()
+    return y.cpu().numpy()
+
+
+def test_plain_eval_fp64_parity(dev, orc):
+    """100,000 isotropic points plus the 64 special points, lmax 9."""
+    pts = workloads.points_plain_eval(seed=0)
+    _say("case: plain eval fp64, n =", pts.shape[0])
+    got = _gpu(dev, 9, pts)
+    ref = orc.eval_xyz(9, pts)
+    err = np.abs(got.astype(LD) - ref).max(axis=1)
+    _say("max abs err per l:", _per_l(err, 9))
+    assert err.max() <= TOL64
+    # the origin (special point 60): R_0^0 = 1/sqrt(4 pi), every other row exactly 0
+    io = pts.shape[0] - 4
+    assert np.all(pts[io] == 0)
+    assert abs(got[0, io] - 1 / math.sqrt(4 * math.pi)) <= 1e-16
+    assert np.all(got[1:, io] == 0)
+
+
+def test_every_lmax(dev, orc):
+    pts = workloads.points_plain_eval(seed=1, n_random=3000)
+    ref = orc.eval_xyz(9, pts)
+    for lmax in range(10):
+        _say("case: lmax", lmax)
+        F = (lmax + 1) ** 2
+        got = _gpu(dev, lmax, pts)
+        assert got.shape == (F, pts.shape[0])
+        assert np.abs(got.astype(LD) - ref[:F]).max() <= TOL64
+        got32 = _gpu(dev, lmax, pts.astype(np.float32), torch.float32)
+        ref32 = orc.eval_xyz(lmax, pts.astype(np.float32))
+        assert np.abs(got32.astype(LD) - ref32).max() <= TOL32
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 255, 256, 257, 1000, 4097])
+def test_ragged_sizes(dev, orc, n):
+    _say("case: ragged n =", n)
+    pts = workloads.isotropic_points(n, 0.1, 5.0, seed=100 + n)
+    x = torch.from_numpy(pts).to(dev)
+    out = torch.full((100, n), float("nan"), dtype=torch.float64, device=dev)
+    sh.sh_eval(9, x, out=out)
+    got = out.cpu().numpy()
+    assert np.isfinite(got).all()
+    assert np.abs(got.astype(LD) - orc.eval_xyz(9, pts)).max() <= TOL64
+
+
+def test_zero_points_is_noop(dev):
+    x = torch.empty((0, 3), dtype=torch.float64, device=dev)
+    y = sh.sh_eval(9, x)
+    torch.cuda.synchronize()
+    assert y.shape == (100, 0)
+
+
+def test_padded_rows_ld(dev, orc):
+    n, ld = 1000, 1037
+    pts = workloads.isotropic_points(n, 0.1, 5.0, seed=7)
+    for dtype, tol in ((torch.float64, TOL64), (torch.float32, TOL32)):
+        _say("case: ld padding", dtype)
+        x = torch.from_numpy(pts).to(dev, dtype)
+        buf = torch.full((49, ld), -7.0, dtype=dtype, device=dev)
+        sh.sh_eval_ld(6, x, buf[:, :n])
+        b = buf.cpu().numpy()
+        assert np.all(b[:, n:] == -7.0)
+        ref = orc.eval_xyz(6, pts if dtype == torch.float64 else pts.astype(np.float32))
+        assert np.abs(b[:, :n].astype(LD) - ref).max() <= tol
+
+
+def test_fp32_parity_per_l(dev, orc):
+    pts = workloads.points_plain_eval(seed=0).astype(np.float32)
+    _say("case: plain eval fp32, n =", pts.shape[0])
+    got = _gpu(dev, 9, pts, torch.float32)
+    ref = orc.eval_xyz(9, pts)
+    err = np.abs(got.astype(LD) - ref).max(axis=1)
+    _say("fp32 max abs err per l:", _per_l(err, 9))
+    assert err.max() <= TOL32
+
+
+def test_bitwise_deterministic(dev):
+    pts = workloads.isotropic_points(50000, 0.1, 5, seed=8)
+    a = _gpu(dev, 9, pts)
+    b = _gpu(dev, 9, pts)
+    assert np.array_equal(a, b)
+
+
+def test_tiny_and_huge_radii(dev, orc):
+    """Squares of these coordinates under- or overflow in double; the kernel's
+    exact power-of-two rescale keeps the direction."""
+    base = workloads.isotropic_points(64, 1.0, 1.0, seed=9)
+    pts = np.concatenate([base * 1e-170, base * 1e170, base * 1e-300, [[0, 0, 1e-200]],
+                          [[3e-310, 0, 0]]])
+    got = _gpu(dev, 9, pts)
+    ref = orc.eval_xyz(9, pts)
+    assert np.abs(got.astype(LD) - ref).max() <= TOL64
+
+
+def test_nan_propagates(dev):
+    pts = np.array([[np.nan, 0.0, 1.0], [1.0, 2.0, 3.0]])
+    got = _gpu(dev, 4, pts)
+    assert np.isnan(got[1:, 0]).all()
+    assert np.isfinite(got[:, 1]).all()
+
+
+_ROOF = {}
+
+
+def _roof_points(n, seed):
+    if (n, seed) not in _ROOF:
+        _ROOF.clear()
+        _ROOF[(n, seed)] = workloads.points_roofline(n=n, seed=seed)
+    return _ROOF[(n, seed)]
+
+
+def _sampled_check(dev, orc, lmax, dtype, n, seed, idx_extra=()):
+    pts = _roof_points(n, seed)
+    x = torch.from_numpy(pts).to(dev, dtype)
+    fn = sh.sh_eval if dtype == torch.float64 else sh.sh_eval_f32
+    y = fn(lmax, x)
+    rng = np.random.default_rng(seed + 1)
+    idx = np.unique(np.concatenate([rng.integers(0, n, 4096), np.arange(64), np.arange(n - 64, n),
+                                    np.asarray(idx_extra, dtype=np.int64)]))
+    it = torch.from_numpy(idx).to(dev)
+    got = y[:, it].cpu().numpy()
+    px = x[it].cpu().numpy()
+    del y, x
+    torch.cuda.empty_cache()
+    ref = orc.eval_xyz(lmax, px)
+    err = np.abs(got.astype(LD) - ref).max(axis=1)
+    return err
+
+
+@pytest.mark.parametrize("lmax", [2, 4, 6, 9])
+def test_roofline_config_full_size_sampled(dev, orc, lmax):
+    """2^26 isotropic points (radius in [0.01, 10]) in the launch shape the
+    benchmark times; sampled columns (random, both ends) against the oracle."""
+    n = 1 << 26
+    for dtype, tol in ((torch.float64, TOL64), (torch.float32, TOL32)):
+        _say("case: 2^26 points, lmax", lmax, dtype)
+        err = _sampled_check(dev, orc, lmax, dtype, n, seed=0)
+        _say("  max abs err per l:", _per_l(err, lmax))
+        assert err.max() <= tol
+
+
+def test_multi_launch_chunking(dev, orc):
+    """More than 2^28 points: the host splits the batch into several launches;
+    check columns on both sides of the split."""
+    n = (1 << 28) + 1000
+    _say("case: chunked launch, n =", n)
+    b = 1 << 28
+    err = _sampled_check(dev, orc, 1, torch.float32, n, seed=3,
+                         idx_extra=np.arange(b - 300, b + 300))
+    _ROOF.clear()
+    assert err.max() <= TOL32
