@@ -71,7 +71,7 @@ def bench_forward(sh, xyz, out, lmax, steps, warmup):
     fn = sh.sh_eval if xyz.dtype == torch.float64 else sh.sh_eval_f32
     F = (lmax + 1) ** 2
     n = xyz.shape[0]
-    o = out.view(-1)[: F * n].view(F, n)
+    o = out.view(-1).view(xyz.dtype)[: F * n].view(F, n)  # reuse the buffer's bytes
     total, per = time_launches(lambda: fn(lmax, xyz, out=o), steps, warmup)
     elem = xyz.element_size()
     avg = sum(per) / len(per)
@@ -126,6 +126,7 @@ def main():
 
     _log("headline: lmax 9 fp64")
     head = bench_forward(sh, xyz, out, 9, args.steps, args.warmup)
+    _log("  ", json.dumps(head))
     result = {
         "metric": "Y_lm points/s (lmax=9, FP64, SoA output) + % HBM peak",
         "value": head["points_per_s"],
@@ -154,6 +155,7 @@ def main():
             _log(f"sweep lmax {lmax}")
             sweep[f"f64_l{lmax}"] = bench_forward(sh, xyz, out, lmax, max(5, args.steps // 2), 2)
             sweep[f"f32_l{lmax}"] = bench_forward(sh, xyz32, out, lmax, max(5, args.steps // 2), 2)
+            _log("  ", json.dumps({k: sweep[k] for k in (f"f64_l{lmax}", f"f32_l{lmax}")}))
         result["fp32"] = sweep["f32_l9"]
         result["lmax_sweep"] = sweep
         _log("write probe")

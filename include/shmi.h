@@ -68,6 +68,147 @@ int sh_eval_f32(int lmax, int64_t n, const float *xyz, float *out, hipStream_t s
 int sh_eval_ld(int lmax, int64_t n, const void *xyz, void *out, int64_t ld, int dtype,
                hipStream_t stream);
 
+/* Backward pass of sh_eval (vector-Jacobian product), for forces:
+ *   grad_xyz[i][k] = sum_{row} grad_out[row][i] * d R_row(x_i) / d x_{i,k}
+ * with xyz [n][3], grad_out [F][n] and grad_xyz [n][3], all double.  The
+ * derivative is that of the unit-vector formulas composed with the
+ * normalisation u = x / |x|: (1/r) (I - u u^T) grad_u.  At r = 0 the gradient
+ * is defined as 0.  grad_xyz is overwritten (not accumulated). */
+int sh_eval_grad(int lmax, int64_t n, const double *xyz, const double *grad_out, double *grad_xyz,
+                 hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Projector build.  The paper's motivating use (Section 1): the angular part of
+ * pseudopotential / PAW projectors on a real-space grid.  For atom a with centre
+ * c_a and grid points p_j, the projector value is
+ *     out_a[row(l,m)][j] = R_l(|d_j|) * R_l^m(d_j / |d_j|),   d_j = p_j - c_a,
+ * where the radial function R_l is a natural cubic spline through values on a
+ * uniform radial grid and is 0 beyond the grid's last knot r_max.
+ */
+typedef struct sh_radial *sh_radial_t;
+
+/* Radial tables: host_values is a HOST array [n_tables][lmax+1][n_r] of R_l at
+ * the knots r_i = i * r_max / (n_r - 1).  The library copies them to the device
+ * and solves the natural-spline second derivatives there (on a private stream;
+ * the call returns when the tables are ready).  The handle owns device memory
+ * until sh_radial_destroy.  SH_EINVAL for lmax outside [0, 9], n_tables < 1,
+ * n_r < 2, r_max not positive and finite, or NULL pointers; SH_ENOMEM when the
+ * device allocation fails. */
+int sh_radial_create(int lmax, int n_tables, int n_r, double r_max, const double *host_values,
+                     sh_radial_t *out);
+
+/* Frees a handle (NULL is a no-op).  No call using it may still be running. */
+int sh_radial_destroy(sh_radial_t radial);
+
+/* Projector arrays for n_atoms atoms whose grid points are concatenated:
+ *   centers        [n_atoms][3]        device
+ *   offsets        [n_atoms + 1] int64 device, CSR: atom a owns points
+ *                  offsets[a] .. offsets[a+1]-1; offsets[0] = 0,
+ *                  offsets[n_atoms] = n_points, nondecreasing
+ *   n_points       host value, the total number of points
+ *   points         [n_points][3]       device, absolute coordinates (periodic
+ *                  images already unwrapped by the caller)
+ *   radial         tables with lmax(radial) >= lmax
+ *   table_of_atom  [n_atoms] int32 device: table used by atom a (clamped to
+ *                  [0, n_tables-1]); NULL means atom a uses table a
+ *   out            [F * n_points] device: atom a's block [F][n_a] starts at
+ *                  out + F * offsets[a] (row stride n_a = its point count)
+ * Device-side arrays are not validated by the host; a point whose offsets are
+ * inconsistent is skipped (nothing is written for it), so no store leaves out. */
+int sh_projectors(int lmax, int n_atoms, const double *centers, const int64_t *offsets, int64_t n_points,
+                  const double *points, sh_radial_t radial, const int32_t *table_of_atom, double *out,
+                  hipStream_t stream);
+
+/* Single-precision twin: float centers, points and out.  d = p - c, |d|, the
+ * normalisation and the spline run in FP64; the harmonics and the product in FP32. */
+int sh_projectors_f32(int lmax, int n_atoms, const float *centers, const int64_t *offsets, int64_t n_points,
+                      const float *points, sh_radial_t radial, const int32_t *table_of_atom, float *out,
+                      hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of projector requests of uneven lmax, point
+ * count and dtype.  Atoms (device point sets with a centre and a radial table)
+ * are registered once and stay on the device.  Each request asks for the
+ * projectors of one atom up to some lmax.  A scheduler thread admits pending
+ * requests in arrival order while their output fits in an HBM budget (carved
+ * from one device allocation made at creation), packs all admitted requests into
+ * one batch and launches it on a free stream slot, so requests that arrive while
+ * others run are admitted as memory and slots free up and their work overlaps on
+ * the device.  Results stay on the device until released.  A request's latency
+ * is measured from sh_server_submit to the host seeing its batch complete.
+ * Every function is thread-safe.
+ */
+typedef struct sh_server *sh_server_t;
+
+#define SH_REQ_AUTORELEASE 1 /* free the output as soon as it is complete (no result) */
+
+enum sh_req_state {
+    SH_REQ_PENDING = 0,  /* waiting for budget */
+    SH_REQ_QUEUED = 1,   /* admitted, output allocated, not yet launched */
+    SH_REQ_RUNNING = 2,  /* in a launched batch */
+    SH_REQ_DONE = 3,     /* result available */
+    SH_REQ_FAILED = 4,   /* its batch failed, or the server shut down first */
+    SH_REQ_RELEASED = 5  /* output returned to the budget */
+};
+
+typedef struct {
+    int64_t submitted, completed, failed;
+    int64_t deferred; /* admitted requests that had waited while the budget was full */
+    int64_t batches;
+    int64_t points_done;
+    uint64_t bytes_in_use, peak_bytes;  /* output bytes admitted (arena) */
+    double first_submit_s, last_done_s; /* seconds since creation; -1 before the first submit */
+} sh_server_stats_t;
+
+/* A server with an HBM budget of budget_bytes (allocated now), at most
+ * max_pending requests waiting for admission (more: SH_EBUSY) and n_slots
+ * batches in flight (1..16, one stream each). */
+int sh_server_create(uint64_t budget_bytes, int max_pending, int n_slots, sh_server_t *out);
+
+/* The same scheduler with a simulated executor that computes nothing: a batch
+ * completes after its output bytes at bytes_per_second, and every fail_every-th
+ * launch (0: never) fails.  For testing the scheduling logic without a GPU;
+ * results are not readable (their addresses are arena offsets). */
+int sh_server_create_simulated(uint64_t budget_bytes, int max_pending, int n_slots, double bytes_per_second,
+                               int fail_every, sh_server_t *out);
+
+/* Refuses new work, fails what was not launched, waits for running batches,
+ * then frees everything (NULL is a no-op). */
+int sh_server_destroy(sh_server_t srv);
+
+/* Registers an atom: n points [n][3] of dtype (device, owned by the caller and
+ * kept valid while the server may use them), centre (host, 3 doubles), table
+ * `table` of `radial` (NULL only for simulated servers). */
+int sh_server_add_atom(sh_server_t srv, int dtype, int64_t n, const void *points, const double *center,
+                       sh_radial_t radial, int table, int *atom_id);
+
+/* Enqueues "projectors of atom_id up to lmax" (output [F][n] of the atom's
+ * dtype).  SH_EBUSY when max_pending requests already wait; SH_EINVAL when the
+ * output could never fit the budget or lmax exceeds the atom's table. */
+int sh_server_submit(sh_server_t srv, int atom_id, int lmax, int flags, int64_t *ticket);
+
+/* Current state (enum sh_req_state) of a request. */
+int sh_server_poll(sh_server_t srv, int64_t ticket, int *state);
+
+/* Waits up to timeout_s seconds for DONE/FAILED/RELEASED; SH_EBUSY on timeout. */
+int sh_server_wait(sh_server_t srv, int64_t ticket, double timeout_s, int *state);
+
+/* Device address of a DONE request's [F][n] output (valid until released).
+ * SH_EBUSY while the request has not finished. */
+int sh_server_result(sh_server_t srv, int64_t ticket, void **out);
+
+/* Returns a finished request's output to the budget (SH_EBUSY if not finished). */
+int sh_server_release(sh_server_t srv, int64_t ticket);
+
+/* Waits until nothing is pending, queued or running; SH_EBUSY on timeout. */
+int sh_server_drain(sh_server_t srv, double timeout_s);
+
+int sh_server_stats(sh_server_t srv, sh_server_stats_t *out);
+
+/* Copies up to cap completed-request latencies (ms, completion order) into
+ * out_ms (may be NULL) and returns how many there are (negative on error). */
+int64_t sh_server_latencies(sh_server_t srv, double *out_ms, int64_t cap);
+
 /* Static text for a status code (never NULL). */
 const char *sh_strerror(int code);
 

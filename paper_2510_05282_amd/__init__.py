@@ -8,6 +8,9 @@ the library's HIP kernels.
 """
 from __future__ import annotations
 
+import ctypes
+
+import numpy as np
 import torch
 
 from ._lib import ShError, check, lib
@@ -16,8 +19,9 @@ SH_LMAX = 9
 SH_F64 = 0
 SH_F32 = 1
 
-__all__ = ["SH_LMAX", "ShError", "nfun", "row", "sh_eval", "sh_eval_f32", "sh_eval_ld",
-           "sh_strerror"]
+__all__ = ["SH_LMAX", "Radial", "ShError", "SphericalHarmonics", "nfun", "row", "sh_eval",
+           "sh_eval_f32", "sh_eval_grad", "sh_eval_ld", "sh_projectors", "sh_projectors_f32",
+           "sh_radial_create", "sh_radial_destroy", "sh_strerror", "spherical_harmonics"]
 
 
 def nfun(lmax: int) -> int:
@@ -93,6 +97,130 @@ def sh_eval_f32(lmax: int, xyz: torch.Tensor, out: torch.Tensor | None = None,
                 stream=None) -> torch.Tensor:
     """Single-precision twin of sh_eval (normalisation still in FP64)."""
     return _eval("sh_eval_f32", torch.float32, lmax, xyz, out, stream)
+
+
+def sh_eval_grad(lmax: int, xyz: torch.Tensor, grad_out: torch.Tensor,
+                 grad_xyz: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Backward of sh_eval: grad_xyz[i, k] = sum_f grad_out[f, i] dR_f(x_i)/dx_{i,k}.
+    xyz [n, 3] and grad_out [F, n] float64 -> [n, 3] float64."""
+    n = _points(xyz, torch.float64)
+    F = nfun(lmax)
+    if (grad_out.dtype != torch.float64 or grad_out.device != xyz.device
+            or tuple(grad_out.shape) != (F, n) or not grad_out.is_contiguous()):
+        raise ValueError(f"grad_out must be a contiguous [{F}, {n}] float64 tensor on {xyz.device}")
+    if grad_xyz is None:
+        grad_xyz = torch.empty((n, 3), dtype=torch.float64, device=xyz.device)
+    elif (grad_xyz.dtype != torch.float64 or grad_xyz.device != xyz.device
+          or tuple(grad_xyz.shape) != (n, 3) or not grad_xyz.is_contiguous()):
+        raise ValueError(f"grad_xyz must be a contiguous [{n}, 3] float64 tensor on {xyz.device}")
+    with torch.cuda.device(xyz.device):
+        check("sh_eval_grad", lib().sh_eval_grad(lmax, n, xyz.data_ptr(), grad_out.data_ptr(),
+                                                 grad_xyz.data_ptr(), _stream(xyz.device, stream)))
+    return grad_xyz
+
+
+class SphericalHarmonics(torch.autograd.Function):
+    """R_l^m(xyz) for l <= lmax as a differentiable op: forward is sh_eval, the
+    gradient with respect to the points is sh_eval_grad (float64)."""
+
+    @staticmethod
+    def forward(ctx, xyz: torch.Tensor, lmax: int) -> torch.Tensor:
+        xyz = xyz.contiguous()
+        ctx.lmax = lmax
+        ctx.save_for_backward(xyz)
+        return sh_eval(lmax, xyz)
+
+    @staticmethod
+    def backward(ctx, grad_out: torch.Tensor):
+        (xyz,) = ctx.saved_tensors
+        return sh_eval_grad(ctx.lmax, xyz, grad_out.contiguous()), None
+
+
+def spherical_harmonics(xyz: torch.Tensor, lmax: int) -> torch.Tensor:
+    """Differentiable real harmonics [F, n] of float64 points [n, 3]."""
+    return SphericalHarmonics.apply(xyz, lmax)
+
+
+class Radial:
+    """Device radial tables (a C `sh_radial_t` handle).  values: host array
+    [n_tables][lmax+1][n_r] of R_l at the knots i * r_max / (n_r - 1)."""
+
+    def __init__(self, values, r_max: float):
+        v = np.ascontiguousarray(values, dtype=np.float64)
+        if v.ndim == 2:
+            v = v[None]
+        if v.ndim != 3:
+            raise ValueError("values must be [n_tables][lmax+1][n_r]")
+        self.n_tables, ch, self.n_r = v.shape
+        self.lmax = ch - 1
+        self.r_max = float(r_max)
+        h = ctypes.c_void_p()
+        check("sh_radial_create", lib().sh_radial_create(self.lmax, self.n_tables, self.n_r, self.r_max,
+                                                        v.ctypes.data, ctypes.byref(h)))
+        self.handle = h
+
+    def close(self) -> None:
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            check("sh_radial_destroy", lib().sh_radial_destroy(self.handle))
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sh_radial_create(values, r_max: float) -> Radial:
+    return Radial(values, r_max)
+
+
+def sh_radial_destroy(radial: Radial) -> None:
+    radial.close()
+
+
+def _projectors(fn: str, dtype, lmax, centers, offsets, points, radial, table_of_atom, out, stream):
+    for name, t in (("centers", centers), ("points", points)):
+        if not t.is_cuda or t.dtype != dtype or t.dim() != 2 or t.shape[1] != 3 or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous [*, 3] {dtype} CUDA tensor")
+    n_atoms = centers.shape[0]
+    if (offsets.dtype != torch.int64 or not offsets.is_cuda or tuple(offsets.shape) != (n_atoms + 1,)
+            or not offsets.is_contiguous()):
+        raise ValueError(f"offsets must be a contiguous int64 CUDA tensor of {n_atoms + 1} entries")
+    n_points = points.shape[0]
+    F = nfun(lmax)
+    if out is None:
+        out = torch.empty(F * n_points, dtype=dtype, device=points.device)
+    elif out.dtype != dtype or out.numel() != F * n_points or not out.is_contiguous():
+        raise ValueError(f"out must be a contiguous {dtype} tensor of {F * n_points} elements")
+    toa = 0
+    if table_of_atom is not None:
+        if (table_of_atom.dtype != torch.int32 or not table_of_atom.is_cuda
+                or tuple(table_of_atom.shape) != (n_atoms,) or not table_of_atom.is_contiguous()):
+            raise ValueError("table_of_atom must be a contiguous int32 CUDA tensor of n_atoms entries")
+        toa = table_of_atom.data_ptr()
+    with torch.cuda.device(points.device):
+        check(fn, getattr(lib(), fn)(lmax, n_atoms, centers.data_ptr(), offsets.data_ptr(), n_points,
+                                     points.data_ptr(), radial.handle, toa or None, out.data_ptr(),
+                                     _stream(points.device, stream)))
+    return out
+
+
+def sh_projectors(lmax: int, centers: torch.Tensor, offsets: torch.Tensor, points: torch.Tensor,
+                  radial: Radial, table_of_atom: torch.Tensor | None = None,
+                  out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Projectors R_l(|p - c_a|) R_l^m(p - c_a) for every atom (float64); returns the
+    flat output in which atom a's [F][n_a] block starts at F * offsets[a]."""
+    return _projectors("sh_projectors", torch.float64, lmax, centers, offsets, points, radial,
+                       table_of_atom, out, stream)
+
+
+def sh_projectors_f32(lmax: int, centers: torch.Tensor, offsets: torch.Tensor, points: torch.Tensor,
+                      radial: Radial, table_of_atom: torch.Tensor | None = None,
+                      out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Single-precision twin of sh_projectors (float32 centers, points, output)."""
+    return _projectors("sh_projectors_f32", torch.float32, lmax, centers, offsets, points, radial,
+                       table_of_atom, out, stream)
 
 
 def sh_strerror(code: int) -> str:

@@ -16,7 +16,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libshmi.so")
-SOURCES = ["sh_api.hip", "sh_eval.hip"]
+SOURCES = ["sh_api.hip", "sh_eval.hip", "sh_grad.hip", "sh_proj.hip", "sh_serve.hip",
+           "sh_server.cpp"]
 ARCH = "gfx950"
 
 
@@ -49,7 +50,7 @@ def build(out_dir: str | None = None, extra: list[str] | None = None) -> str:
     extra = list(extra or [])
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
-    objs = [os.path.join(bdir, s.replace(".hip", ".o")) for s in SOURCES]
+    objs = [os.path.join(bdir, os.path.splitext(s)[0] + ".o") for s in SOURCES]
     with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         futs = [ex.submit(_compile, os.path.join(CSRC, s), o, extra) for s, o in zip(SOURCES, objs)]
         for f in futs:

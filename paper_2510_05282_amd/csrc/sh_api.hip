@@ -1,9 +1,19 @@
 // sh_api.hip -- the C ABI: argument validation and dispatch to the kernels.
 #include <hip/hip_runtime.h>
+#include <math.h>
 #include <stdint.h>
+
+#include <memory>
+#include <new>
 
 #include "../../include/shmi.h"
 #include "sh_internal.h"
+#include "sh_server.h"
+
+struct sh_server {
+    std::unique_ptr<shs::Server> srv;
+    bool simulated;
+};
 
 namespace {
 
@@ -17,6 +27,20 @@ int hip_status(hipError_t e)
 }
 
 bool bad_lmax(int lmax) { return lmax < 0 || lmax > SH_LMAX; }
+
+template <typename TIO>
+static int projectors(int lmax, int n_atoms, const TIO *centers, const int64_t *offsets, int64_t n_points,
+                      const TIO *points, sh_radial_t radial, const int32_t *table_of_atom, TIO *out,
+                      hipStream_t stream)
+{
+    if (bad_lmax(lmax) || n_atoms < 0 || n_points < 0 || !radial || radial->lmax < lmax) return SH_EINVAL;
+    if (n_points == 0) return SH_OK;
+    if (n_atoms == 0 || !centers || !offsets || !points || !out) return SH_EINVAL;
+    if (!table_of_atom && radial->n_tables < n_atoms) return SH_EINVAL;
+    shk::ProjArgs<TIO> A{centers, offsets, n_atoms, points, n_points, radial->table, radial->lmax + 1,
+                         radial->n_tables, table_of_atom, radial->n_r, radial->h, radial->r_max, out};
+    return hip_status(shk::launch_projectors<TIO>(lmax, A, stream));
+}
 
 }  // namespace
 
@@ -57,6 +81,212 @@ int sh_eval(int lmax, int64_t n, const double *xyz, double *out, hipStream_t str
 int sh_eval_f32(int lmax, int64_t n, const float *xyz, float *out, hipStream_t stream)
 {
     return sh_eval_ld(lmax, n, xyz, out, n, SH_F32, stream);
+}
+
+int sh_eval_grad(int lmax, int64_t n, const double *xyz, const double *grad_out, double *grad_xyz,
+                 hipStream_t stream)
+{
+    if (bad_lmax(lmax) || n < 0) return SH_EINVAL;
+    if (n == 0) return SH_OK;
+    if (!xyz || !grad_out || !grad_xyz) return SH_EINVAL;
+    return hip_status(shk::launch_grad(lmax, n, xyz, grad_out, n, grad_xyz, stream));
+}
+
+int sh_radial_create(int lmax, int n_tables, int n_r, double r_max, const double *host_values, sh_radial_t *out)
+{
+    if (!out) return SH_EINVAL;
+    *out = nullptr;
+    if (bad_lmax(lmax) || n_tables < 1 || n_r < 2 || !(r_max > 0.0) || !isfinite(r_max) || !host_values)
+        return SH_EINVAL;
+    const int64_t n_ch = int64_t(n_tables) * (lmax + 1);
+    const int64_t nval = n_ch * n_r;
+    if (n_ch > 0x7fffffff || nval > (int64_t(1) << 34)) return SH_EINVAL;
+    double2 *table = nullptr;
+    double *y = nullptr, *scratch = nullptr;
+    hipStream_t st = nullptr;
+    int rc = SH_OK;
+    hipError_t e;
+    if (hipMalloc(&table, sizeof(double2) * nval) != hipSuccess ||
+        hipMalloc(&y, sizeof(double) * nval) != hipSuccess ||
+        hipMalloc(&scratch, sizeof(double) * nval) != hipSuccess) {
+        (void)hipGetLastError();
+        rc = SH_ENOMEM;
+        goto done;
+    }
+    e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipMemcpyAsync(y, host_values, sizeof(double) * nval, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = shk::launch_spline_setup(y, table, scratch, int(n_ch), n_r, r_max / double(n_r - 1), st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    rc = hip_status(e);
+done:
+    if (st) (void)hipStreamDestroy(st);
+    if (y) (void)hipFree(y);
+    if (scratch) (void)hipFree(scratch);
+    if (rc != SH_OK) {
+        if (table) (void)hipFree(table);
+        return rc;
+    }
+    sh_radial *h = new (std::nothrow) sh_radial{lmax, n_tables, n_r, r_max, r_max / double(n_r - 1), table};
+    if (!h) {
+        (void)hipFree(table);
+        return SH_ENOMEM;
+    }
+    *out = h;
+    return SH_OK;
+}
+
+int sh_radial_destroy(sh_radial_t radial)
+{
+    if (!radial) return SH_OK;
+    hipError_t e = hipFree(radial->table);
+    delete radial;
+    return hip_status(e);
+}
+
+int sh_projectors(int lmax, int n_atoms, const double *centers, const int64_t *offsets, int64_t n_points,
+                  const double *points, sh_radial_t radial, const int32_t *table_of_atom, double *out,
+                  hipStream_t stream)
+{
+    return projectors<double>(lmax, n_atoms, centers, offsets, n_points, points, radial, table_of_atom, out,
+                              stream);
+}
+
+int sh_projectors_f32(int lmax, int n_atoms, const float *centers, const int64_t *offsets, int64_t n_points,
+                      const float *points, sh_radial_t radial, const int32_t *table_of_atom, float *out,
+                      hipStream_t stream)
+{
+    return projectors<float>(lmax, n_atoms, centers, offsets, n_points, points, radial, table_of_atom, out,
+                             stream);
+}
+
+// ---------------------------------------------------------------- serving
+
+static int server_new(std::unique_ptr<shs::Executor> ex, uint64_t budget, int max_pending, bool sim,
+                      sh_server_t *out)
+{
+    sh_server *h = new (std::nothrow) sh_server{};
+    if (!h) return SH_ENOMEM;
+    h->simulated = sim;
+    h->srv.reset(new (std::nothrow) shs::Server(std::move(ex), budget, max_pending));
+    if (!h->srv) {
+        delete h;
+        return SH_ENOMEM;
+    }
+    *out = h;
+    return SH_OK;
+}
+
+int sh_server_create(uint64_t budget_bytes, int max_pending, int n_slots, sh_server_t *out)
+{
+    if (!out) return SH_EINVAL;
+    *out = nullptr;
+    if (budget_bytes < 256 || max_pending < 1 || n_slots < 1 || n_slots > 16) return SH_EINVAL;
+    int st = SH_OK;
+    std::unique_ptr<shs::Executor> ex = shs::make_hip_executor(budget_bytes, n_slots, &st);
+    if (!ex) return st == SH_OK ? SH_EHIP : st;
+    return server_new(std::move(ex), budget_bytes, max_pending, false, out);
+}
+
+int sh_server_create_simulated(uint64_t budget_bytes, int max_pending, int n_slots, double bytes_per_second,
+                               int fail_every, sh_server_t *out)
+{
+    if (!out) return SH_EINVAL;
+    *out = nullptr;
+    if (budget_bytes < 256 || max_pending < 1 || n_slots < 1 || n_slots > 16 || !(bytes_per_second > 0.0))
+        return SH_EINVAL;
+    return server_new(shs::make_sim_executor(budget_bytes, n_slots, bytes_per_second, fail_every), budget_bytes,
+                      max_pending, true, out);
+}
+
+int sh_server_destroy(sh_server_t srv)
+{
+    delete srv;
+    return SH_OK;
+}
+
+int sh_server_add_atom(sh_server_t srv, int dtype, int64_t n, const void *points, const double *center,
+                       sh_radial_t radial, int table, int *atom_id)
+{
+    if (!srv || !center || !atom_id || !points || n <= 0) return SH_EINVAL;
+    if (dtype != SH_F64 && dtype != SH_F32) return SH_EINVAL;
+    shs::Atom a{};
+    a.dtype = dtype;
+    a.n = n;
+    a.points = points;
+    for (int q = 0; q < 3; ++q) a.c[q] = center[q];
+    if (radial) {
+        if (table < 0 || table >= radial->n_tables) return SH_EINVAL;
+        a.tab = radial->table + int64_t(table) * (radial->lmax + 1) * radial->n_r;
+        a.tab_lmax = radial->lmax;
+        a.n_r = radial->n_r;
+        a.h = radial->h;
+        a.r_max = radial->r_max;
+    } else {
+        if (!srv->simulated) return SH_EINVAL;
+        a.tab_lmax = SH_LMAX;
+    }
+    return srv->srv->add_atom(a, atom_id);
+}
+
+int sh_server_submit(sh_server_t srv, int atom_id, int lmax, int flags, int64_t *ticket)
+{
+    if (!srv) return SH_EINVAL;
+    return srv->srv->submit(atom_id, lmax, flags, ticket);
+}
+
+int sh_server_poll(sh_server_t srv, int64_t ticket, int *state)
+{
+    if (!srv) return SH_EINVAL;
+    return srv->srv->poll(ticket, state);
+}
+
+int sh_server_wait(sh_server_t srv, int64_t ticket, double timeout_s, int *state)
+{
+    if (!srv || !(timeout_s >= 0.0)) return SH_EINVAL;
+    return srv->srv->wait(ticket, timeout_s, state);
+}
+
+int sh_server_result(sh_server_t srv, int64_t ticket, void **out)
+{
+    if (!srv) return SH_EINVAL;
+    return srv->srv->result(ticket, out);
+}
+
+int sh_server_release(sh_server_t srv, int64_t ticket)
+{
+    if (!srv) return SH_EINVAL;
+    return srv->srv->release(ticket);
+}
+
+int sh_server_drain(sh_server_t srv, double timeout_s)
+{
+    if (!srv || !(timeout_s >= 0.0)) return SH_EINVAL;
+    return srv->srv->drain(timeout_s);
+}
+
+int sh_server_stats(sh_server_t srv, sh_server_stats_t *out)
+{
+    if (!srv || !out) return SH_EINVAL;
+    shs::Stats s;
+    srv->srv->stats(&s);
+    out->submitted = s.submitted;
+    out->completed = s.completed;
+    out->failed = s.failed;
+    out->deferred = s.deferred;
+    out->batches = s.batches;
+    out->points_done = s.points_done;
+    out->bytes_in_use = s.bytes_in_use;
+    out->peak_bytes = s.peak_bytes;
+    out->first_submit_s = s.first_submit_s;
+    out->last_done_s = s.last_done_s;
+    return SH_OK;
+}
+
+int64_t sh_server_latencies(sh_server_t srv, double *out_ms, int64_t cap)
+{
+    if (!srv || cap < 0) return -SH_EINVAL;
+    return srv->srv->latencies(out_ms, cap);
 }
 
 }  // extern "C"

@@ -8,6 +8,10 @@
 // (sh_constants.h documents the three factors).  Z_lm is shared by +m and -m,
 // so each z-polynomial is evaluated once per point rather than once per sign of m.
 //
+// The arithmetic type T may be a scalar (double, float) or a clang vector of
+// them (double2, float4, ...): a vector evaluates that many points at once,
+// lane-wise, so adjacent points of one thread share every instruction.
+//
 // Row of (l, m) in every output: l*l + l + m.
 #pragma once
 
@@ -32,7 +36,16 @@ __host__ __device__ __forceinline__ void static_for(F&& f)
     }
 }
 
-// Constants in the arithmetic type of the polynomials.
+// Scalar type of a (possibly vector) arithmetic type.
+template <typename T> struct scalar_of { using type = T; };
+template <typename S, int N> struct scalar_of<S __attribute__((ext_vector_type(N)))> { using type = S; };
+template <typename T> using scalar_t = typename scalar_of<T>::type;
+
+typedef double double2_t __attribute__((ext_vector_type(2)));
+typedef float float2_t __attribute__((ext_vector_type(2)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+// Constants in the scalar type of the polynomials.
 template <typename T> struct K;
 template <> struct K<double> {
     static __host__ __device__ constexpr double zroot(int l, int m, int k) { return shc::kZRoot[l][m][k]; }
@@ -51,8 +64,8 @@ template <> struct K<float> {
 
 // Pair factor p(a, b) = (a - b)(a + b), eq. rpair: kept as a product of the two
 // root factors rather than a^2 - b^2.
-template <typename T>
-__host__ __device__ __forceinline__ T pf(T a, T b) { return (a - b) * (a + b); }
+template <typename A, typename B>
+__host__ __device__ __forceinline__ auto pf(A a, B b) { return (a - b) * (a + b); }
 
 // Shat_m(x, y) = y * x^[m even] * prod_{k=1}^{ceil(m/2)-1} p(tan(k pi/m) x, y).
 template <typename T, int M>
@@ -62,7 +75,7 @@ __host__ __device__ __forceinline__ T shat(T x, T y)
     if constexpr (M % 2 == 0) acc *= x;
     static_for<0, (M + 1) / 2 - 1>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
-        acc *= pf(K<T>::tans(M, k) * x, y);
+        acc *= pf(K<scalar_t<T>>::tans(M, k) * x, y);
     });
     return acc;
 }
@@ -75,7 +88,7 @@ __host__ __device__ __forceinline__ T chat(T x, T y)
     if constexpr (M % 2 == 1) acc = x;
     static_for<0, M / 2>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
-        const T f = pf(K<T>::tanc(M, k) * x, y);
+        const T f = pf(K<scalar_t<T>>::tanc(M, k) * x, y);
         if constexpr (k == 0 && M % 2 == 0) acc = f;
         else acc *= f;
     });
@@ -90,12 +103,12 @@ __host__ __device__ __forceinline__ T zfac(T z)
     constexpr bool odd = ((L - M) & 1) != 0;
     if constexpr (np == 0) {
         if constexpr (odd) return z;
-        else return T(1);
+        else return T(scalar_t<T>(1));
     } else {
-        T acc = pf(K<T>::zroot(L, M, 0), z);
+        T acc = pf(K<scalar_t<T>>::zroot(L, M, 0), z);
         static_for<1, np>([&](auto kc) {
             constexpr int k = decltype(kc)::value;
-            acc *= pf(K<T>::zroot(L, M, k), z);
+            acc *= pf(K<scalar_t<T>>::zroot(L, M, k), z);
         });
         if constexpr (odd) acc *= z;
         return acc;
@@ -111,12 +124,13 @@ template <int LMAX, typename T, typename Sink>
 __host__ __device__ __forceinline__ void eval_unit(T x, T y, T z, T keep, Sink&& sink)
 {
     static_assert(LMAX >= 0 && LMAX <= shc::kLmax, "lmax out of range");
+    using KS = K<scalar_t<T>>;
     static_for<0, LMAX + 1>([&](auto mc) {
         constexpr int M = decltype(mc)::value;
         if constexpr (M == 0) {
             static_for<0, LMAX + 1>([&](auto lc) {
                 constexpr int L = decltype(lc)::value;
-                T v = K<T>::a(L, 0) * zfac<T, L, 0>(z);
+                T v = KS::a(L, 0) * zfac<T, L, 0>(z);
                 if constexpr (L > 0 && L % 2 == 0) v *= keep;
                 sink(row(L, 0), v);
             });
@@ -126,8 +140,8 @@ __host__ __device__ __forceinline__ void eval_unit(T x, T y, T z, T keep, Sink&&
             static_for<M, LMAX + 1>([&](auto lc) {
                 constexpr int L = decltype(lc)::value;
                 const T zf = zfac<T, L, M>(z);
-                sink(row(L, -M), K<T>::a(L, M) * zf * s);
-                sink(row(L, M), K<T>::b(L, M) * zf * c);
+                sink(row(L, -M), KS::a(L, M) * zf * s);
+                sink(row(L, M), KS::b(L, M) * zf * c);
             });
         }
     });
@@ -148,24 +162,35 @@ __device__ __forceinline__ double rsqrt_refined(double a)
 // Unit vector of (x, y, z) in double, with the near-origin guard: coordinates
 // whose squares would underflow (or overflow) are first scaled by an exact power
 // of two, which leaves the direction unchanged.  At exactly r = 0 the unit vector
-// is returned as 0 and keep = 0.  NaN propagates.
-__device__ __forceinline__ void normalize(double x, double y, double z,
-                                          double& xb, double& yb, double& zb, double& keep)
+// is returned as 0 and keep = 0.  A NaN coordinate makes every component NaN.
+// rinv receives 1/r of the unscaled point (0 at the origin; it overflows to inf
+// only when r itself is below the smallest normal double).
+__device__ __forceinline__ void normalize(double x, double y, double z, double& xb, double& yb,
+                                          double& zb, double& keep, double& rinv)
 {
     const double mx = fmax(fabs(x), fmax(fabs(y), fabs(z)));
+    double s = 1.0;
     if (mx < 0x1p-500 || mx > 0x1p+500) {
-        const double s = mx < 0x1p-500 ? 0x1p+600 : 0x1p-600;
+        s = mx < 0x1p-500 ? 0x1p+600 : 0x1p-600;
         x *= s;
         y *= s;
         z *= s;
     }
     const double r2 = __builtin_fma(x, x, __builtin_fma(y, y, z * z));
     const bool nz = r2 > 0.0;
-    const double ri = nz ? rsqrt_refined(r2) : 0.0;
+    const double ri = nz ? rsqrt_refined(r2) : r2 * 0.0;  // 0 at the origin, NaN for NaN
     xb = x * ri;
     yb = y * ri;
     zb = z * ri;
     keep = nz ? 1.0 : 0.0;
+    rinv = ri * s;
+}
+
+__device__ __forceinline__ void normalize(double x, double y, double z, double& xb, double& yb,
+                                          double& zb, double& keep)
+{
+    double rinv;
+    normalize(x, y, z, xb, yb, zb, keep, rinv);
 }
 
 }  // namespace shk

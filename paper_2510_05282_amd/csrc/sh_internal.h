@@ -4,10 +4,49 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// Radial tables owned by the library (opaque to C callers as `struct sh_radial`).
+struct sh_radial {
+    int lmax;      // channels per table - 1
+    int n_tables;  // tables in this handle
+    int n_r;       // knots per channel (uniform grid on [0, r_max])
+    double r_max;
+    double h;      // knot spacing r_max / (n_r - 1)
+    double2* table;  // device, [n_tables][lmax+1][n_r] of (y, M)
+};
+
 namespace shk {
 
 // Forward values R_l^m for l <= lmax at n points xyz[n][3] into out[F][ld].
 template <typename TIO>
 hipError_t launch_fwd(int lmax, int64_t n, const TIO* xyz, TIO* out, int64_t ld, hipStream_t s);
+
+// Vector-Jacobian product: gxyz[n][3] = sum_f G[f][i] dR_f/dx at xyz[n][3]; G is [F][ldg].
+hipError_t launch_grad(int lmax, int64_t n, const double* xyz, const double* G, int64_t ldg, double* gxyz,
+                       hipStream_t s);
+
+// Arguments of the flat projector kernel (device pointers unless noted).
+template <typename TIO>
+struct ProjArgs {
+    const TIO* centers;            // [n_atoms][3]
+    const int64_t* offsets;        // [n_atoms+1] CSR over points
+    int n_atoms;
+    const TIO* points;             // [n_points][3]
+    int64_t n_points;
+    const double2* table;          // radial handle's tables
+    int tab_ch;                    // channels per table
+    int n_tables;
+    const int32_t* table_of_atom;  // [n_atoms] or null (atom a uses table a)
+    int n_r;
+    double h, r_max;
+    TIO* out;                      // atom a's [F][n_a] block at out + F * offsets[a]
+};
+
+template <typename TIO>
+hipError_t launch_projectors(int lmax, const ProjArgs<TIO>& A, hipStream_t s);
+
+// Natural-spline second derivatives for n_ch channels of n_r values y (device):
+// writes (y, M) pairs to table; scratch holds n_ch * n_r doubles.
+hipError_t launch_spline_setup(const double* y, double2* table, double* scratch, int n_ch, int n_r, double h,
+                               hipStream_t s);
 
 }  // namespace shk

@@ -1,0 +1,378 @@
+// sh_server.cpp -- scheduling core of the projector server and its simulated
+// executor (host code only; the HIP executor lives in sh_serve.hip).
+#include "sh_server.h"
+
+#include <algorithm>
+
+#include "../../include/shmi.h"
+
+namespace shs {
+
+// ---------------------------------------------------------------- arena
+
+Arena::Arena(uint64_t capacity) : cap_(capacity & ~uint64_t(255))
+{
+    if (cap_) free_[0] = cap_;
+}
+
+bool Arena::alloc(uint64_t bytes, uint64_t* offset)
+{
+    bytes = round(bytes ? bytes : 1);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+        if (it->second >= bytes) {
+            const uint64_t off = it->first, rest = it->second - bytes;
+            free_.erase(it);
+            if (rest) free_[off + bytes] = rest;
+            used_ += bytes;
+            *offset = off;
+            return true;
+        }
+    }
+    return false;
+}
+
+void Arena::release(uint64_t offset, uint64_t bytes)
+{
+    bytes = round(bytes ? bytes : 1);
+    used_ -= bytes;
+    auto it = free_.emplace(offset, bytes).first;
+    auto next = std::next(it);
+    if (next != free_.end() && it->first + it->second == next->first) {
+        it->second += next->second;
+        free_.erase(next);
+    }
+    if (it != free_.begin()) {
+        auto prev = std::prev(it);
+        if (prev->first + prev->second == it->first) {
+            prev->second += it->second;
+            free_.erase(it);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- server
+
+static uint64_t out_bytes(const Atom& a, int lmax)
+{
+    return uint64_t(lmax + 1) * uint64_t(lmax + 1) * uint64_t(a.n) * (a.dtype == SH_F64 ? 8u : 4u);
+}
+
+static double secs(Clock::duration d) { return std::chrono::duration<double>(d).count(); }
+
+static void* at(void* base, uint64_t offset)
+{
+    return reinterpret_cast<void*>(reinterpret_cast<uintptr_t>(base) + offset);
+}
+
+Server::Server(std::unique_ptr<Executor> ex, uint64_t budget, int64_t max_pending)
+    : ex_(std::move(ex)), arena_(budget), max_pending_(max_pending), t0_(Clock::now())
+{
+    const int ns = ex_->n_slots();
+    slot_reqs_.resize(ns);
+    for (int s = ns - 1; s >= 0; --s) free_slots_.push_back(s);
+    st_.first_submit_s = -1.0;
+    thr_ = std::thread([this] { loop(); });
+}
+
+Server::~Server()
+{
+    {
+        std::lock_guard<std::mutex> g(mu_);
+        stop_ = true;
+        gen_++;
+    }
+    cv_work_.notify_all();
+    thr_.join();
+}
+
+int Server::add_atom(const Atom& a, int* id)
+{
+    if (!id || a.n <= 0 || !a.points || (a.dtype != SH_F64 && a.dtype != SH_F32)) return SH_EINVAL;
+    std::lock_guard<std::mutex> g(mu_);
+    atoms_.push_back(a);
+    *id = int(atoms_.size() - 1);
+    return SH_OK;
+}
+
+int Server::submit(int atom, int lmax, int flags, int64_t* ticket)
+{
+    if (!ticket || lmax < 0 || lmax > SH_LMAX) return SH_EINVAL;
+    std::lock_guard<std::mutex> g(mu_);
+    if (stop_) return SH_EBUSY;
+    if (atom < 0 || atom >= int(atoms_.size())) return SH_EINVAL;
+    const Atom& a = atoms_[atom];
+    if (a.tab && lmax > a.tab_lmax) return SH_EINVAL;
+    const uint64_t bytes = out_bytes(a, lmax);
+    if (Arena::round(bytes) > arena_.capacity()) return SH_EINVAL;  // could never be admitted
+    if (int64_t(pending_.size()) >= max_pending_) return SH_EBUSY;
+    Request r{};
+    r.atom = atom;
+    r.lmax = lmax;
+    r.flags = flags;
+    r.bytes = bytes;
+    r.state = kPending;
+    r.t_submit = Clock::now();
+    r.refusals_at_submit = refusals_;
+    *ticket = int64_t(reqs_.size());
+    reqs_.push_back(r);
+    pending_.push_back(*ticket);
+    gen_++;
+    st_.submitted++;
+    if (st_.first_submit_s < 0) st_.first_submit_s = secs(r.t_submit - t0_);
+    cv_work_.notify_one();
+    return SH_OK;
+}
+
+bool Server::admit_locked()
+{
+    bool prog = false;
+    while (!pending_.empty()) {
+        Request& r = reqs_[pending_.front()];
+        uint64_t off;
+        if (!arena_.alloc(r.bytes, &off)) {
+            refusals_++;
+            break;
+        }
+        // deferred: a refusal for lack of budget happened while it was waiting
+        if (refusals_ > r.refusals_at_submit) st_.deferred++;
+        r.offset = off;
+        r.state = kQueued;
+        queued_.push_back(pending_.front());
+        pending_.pop_front();
+        st_.bytes_in_use = arena_.in_use();
+        st_.peak_bytes = std::max(st_.peak_bytes, st_.bytes_in_use);
+        prog = true;
+    }
+    return prog;
+}
+
+void Server::finish_locked(int slot, int status)
+{
+    const Clock::time_point now = Clock::now();
+    for (int64_t t : slot_reqs_[slot]) {
+        Request& r = reqs_[t];
+        r.t_done = now;
+        if (status == SH_OK) {
+            r.state = kDone;
+            st_.completed++;
+            st_.points_done += atoms_[r.atom].n;
+            lat_ms_.push_back(secs(r.t_done - r.t_submit) * 1e3);
+            st_.last_done_s = secs(now - t0_);
+            if (r.flags & SH_REQ_AUTORELEASE) {
+                arena_.release(r.offset, r.bytes);
+                r.state = kReleased;
+            }
+        } else {
+            r.state = kFailed;
+            r.error = status;
+            st_.failed++;
+            arena_.release(r.offset, r.bytes);
+        }
+    }
+    st_.bytes_in_use = arena_.in_use();
+    slot_reqs_[slot].clear();
+    free_slots_.push_back(slot);
+    cv_done_.notify_all();
+}
+
+bool Server::reap_locked()
+{
+    bool prog = false;
+    for (int s = 0; s < int(slot_reqs_.size()); ++s) {
+        if (slot_reqs_[s].empty()) continue;
+        const int q = ex_->query(s);
+        if (q == 0) continue;
+        busy_slots_--;
+        finish_locked(s, q > 0 ? SH_OK : SH_EHIP);
+        prog = true;
+    }
+    return prog;
+}
+
+void Server::loop()
+{
+    std::unique_lock<std::mutex> lk(mu_);
+    for (;;) {
+        bool prog = reap_locked();
+        if (stop_) {
+            // refuse what has not started; let running batches finish
+            for (int64_t t : pending_) {
+                reqs_[t].state = kFailed;
+                reqs_[t].error = SH_EBUSY;
+            }
+            for (int64_t t : queued_) {
+                reqs_[t].state = kFailed;
+                reqs_[t].error = SH_EBUSY;
+                arena_.release(reqs_[t].offset, reqs_[t].bytes);
+            }
+            pending_.clear();
+            queued_.clear();
+            cv_done_.notify_all();
+            if (busy_slots_ == 0) break;
+        } else {
+            prog |= admit_locked();
+        }
+        if (!queued_.empty() && !free_slots_.empty()) {
+            const int slot = free_slots_.back();
+            free_slots_.pop_back();
+            std::vector<Item> items;
+            int64_t tiles = 0;
+            size_t k = 0;
+            for (; k < queued_.size() && int64_t(items.size()) < ex_->max_items(); ++k) {
+                Request& r = reqs_[queued_[k]];
+                const Atom& a = atoms_[r.atom];
+                const int64_t nt = (a.n + 255) / 256;
+                if (!items.empty() && tiles + nt > ex_->max_tiles()) break;
+                tiles += nt;
+                items.push_back(Item{a, r.lmax, at(ex_->arena_base(), r.offset)});
+                r.state = kRunning;
+                slot_reqs_[slot].push_back(queued_[k]);
+            }
+            queued_.erase(queued_.begin(), queued_.begin() + k);
+            lk.unlock();
+            const int rc = ex_->launch(slot, items);
+            lk.lock();
+            if (rc != SH_OK) {
+                finish_locked(slot, rc);
+            } else {
+                busy_slots_++;
+                st_.batches++;
+            }
+            prog = true;
+        }
+        if (!prog) {
+            if (busy_slots_ > 0) {
+                lk.unlock();
+                std::this_thread::yield();
+                lk.lock();
+            } else {
+                // nothing runs and nothing can be admitted: sleep until a submit,
+                // a release or shutdown changes the picture
+                const uint64_t g = gen_;
+                cv_work_.wait(lk, [&] { return stop_ || gen_ != g; });
+            }
+        }
+    }
+}
+
+int Server::poll(int64_t ticket, int* state)
+{
+    if (!state) return SH_EINVAL;
+    std::lock_guard<std::mutex> g(mu_);
+    if (ticket < 0 || ticket >= int64_t(reqs_.size())) return SH_EINVAL;
+    *state = reqs_[ticket].state;
+    return SH_OK;
+}
+
+int Server::wait(int64_t ticket, double timeout_s, int* state)
+{
+    std::unique_lock<std::mutex> lk(mu_);
+    if (ticket < 0 || ticket >= int64_t(reqs_.size())) return SH_EINVAL;
+    const bool ok = cv_done_.wait_for(lk, std::chrono::duration<double>(timeout_s),
+                                      [&] { return reqs_[ticket].state >= kDone; });
+    if (state) *state = reqs_[ticket].state;
+    return ok ? SH_OK : SH_EBUSY;
+}
+
+int Server::result(int64_t ticket, void** ptr)
+{
+    if (!ptr) return SH_EINVAL;
+    std::lock_guard<std::mutex> g(mu_);
+    if (ticket < 0 || ticket >= int64_t(reqs_.size())) return SH_EINVAL;
+    const Request& r = reqs_[ticket];
+    if (r.state < kDone) return SH_EBUSY;
+    if (r.state != kDone) return r.state == kFailed ? r.error : SH_EINVAL;
+    *ptr = at(ex_->arena_base(), r.offset);
+    return SH_OK;
+}
+
+int Server::release(int64_t ticket)
+{
+    std::lock_guard<std::mutex> g(mu_);
+    if (ticket < 0 || ticket >= int64_t(reqs_.size())) return SH_EINVAL;
+    Request& r = reqs_[ticket];
+    if (r.state < kDone) return SH_EBUSY;
+    if (r.state == kDone) {
+        arena_.release(r.offset, r.bytes);
+        st_.bytes_in_use = arena_.in_use();
+        gen_++;
+        cv_work_.notify_one();
+    }
+    r.state = kReleased;
+    return SH_OK;
+}
+
+int Server::drain(double timeout_s)
+{
+    std::unique_lock<std::mutex> lk(mu_);
+    const bool ok = cv_done_.wait_for(lk, std::chrono::duration<double>(timeout_s), [&] {
+        return pending_.empty() && queued_.empty() && busy_slots_ == 0;
+    });
+    return ok ? SH_OK : SH_EBUSY;
+}
+
+void Server::stats(Stats* s)
+{
+    std::lock_guard<std::mutex> g(mu_);
+    *s = st_;
+}
+
+int64_t Server::latencies(double* out, int64_t cap)
+{
+    std::lock_guard<std::mutex> g(mu_);
+    const int64_t n = std::min<int64_t>(cap, int64_t(lat_ms_.size()));
+    if (out)
+        for (int64_t i = 0; i < n; ++i) out[i] = lat_ms_[i];
+    return int64_t(lat_ms_.size());
+}
+
+// ---------------------------------------------------------------- simulation
+
+namespace {
+
+// Runs nothing: a batch "finishes" after its output bytes at a fixed rate, and
+// every fail_every-th launch reports a failure.  Used to test scheduling without
+// a GPU; its arena has no memory (base address 0, offsets only).
+class SimExecutor final : public Executor {
+public:
+    SimExecutor(int n_slots, double bps, int fail_every)
+        : done_at_(n_slots), fail_(n_slots, false), bps_(bps), fail_every_(fail_every)
+    {
+    }
+    int n_slots() const override { return int(done_at_.size()); }
+    int64_t max_items() const override { return 4096; }
+    int64_t max_tiles() const override { return int64_t(1) << 22; }
+    void* arena_base() override { return nullptr; }
+    int launch(int slot, const std::vector<Item>& items) override
+    {
+        double bytes = 0;
+        for (const Item& it : items) bytes += double(out_bytes(it.atom, it.lmax));
+        done_at_[slot] = Clock::now() + std::chrono::duration_cast<Clock::duration>(
+                                            std::chrono::duration<double>(bytes / bps_));
+        ++launches_;
+        fail_[slot] = fail_every_ > 0 && launches_ % fail_every_ == 0;
+        return SH_OK;
+    }
+    int query(int slot) override
+    {
+        if (Clock::now() < done_at_[slot]) return 0;
+        return fail_[slot] ? -1 : 1;
+    }
+
+private:
+    std::vector<Clock::time_point> done_at_;
+    std::vector<bool> fail_;
+    double bps_;
+    int fail_every_;
+    int64_t launches_ = 0;
+};
+
+}  // namespace
+
+std::unique_ptr<Executor> make_sim_executor(uint64_t budget, int n_slots, double bytes_per_s, int fail_every)
+{
+    (void)budget;
+    return std::unique_ptr<Executor>(new SimExecutor(n_slots, bytes_per_s, fail_every));
+}
+
+}  // namespace shs

@@ -3,8 +3,9 @@
 This module only draws inputs (points, atom spheres, radial tables, request
 streams).  It holds none of the harmonic, spline or projector arithmetic, and it
 is the one piece of code that both the GPU path's tests/benchmark and the CPU
-oracle's tests use.  All randomness comes from ``numpy.random.default_rng(seed)``
-(PCG64).
+oracle's tests use.  Randomness comes from ``numpy.random.default_rng(seed)``
+(PCG64), except the large upstream gradients of `upstream_gradient_device`,
+which torch's seeded generator draws on the device.
 
 The paper samples random points for its accuracy study (Section 4) and random
 perturbed points for its timings (Section 5); it fixes no dataset.  The shapes here
@@ -82,14 +83,16 @@ def upstream_gradient(nfun: int, n: int, seed: int = 1) -> np.ndarray:
 def radial_table(rng: np.random.Generator, lmax: int, n_r: int = 2000,
                  r_max: float = 3.0) -> np.ndarray:
     """[(lmax+1)][n_r] radial values on the uniform grid r_i = i r_max/(n_r-1):
-    R_l(r) = sum_{k=0..2} c_lk r^(l+2k) exp(-a_lk r^2), c ~ N(0,1),
-    a ~ U[0.5, 2], rescaled so that max_i |R_l(r_i)| = 1."""
+    R_l(r) = (1 - (r/r_max)^2)^2 sum_{k=0..2} c_lk r^(l+2k) exp(-a_lk r^2),
+    c ~ N(0,1), a ~ U[0.5, 2], rescaled so that max_i |R_l(r_i)| = 1.  Like a
+    pseudopotential projector, each R_l goes smoothly to zero at the cutoff r_max."""
     r = np.linspace(0.0, r_max, n_r)
+    cut = (1.0 - (r / r_max) ** 2) ** 2
     out = np.empty((lmax + 1, n_r))
     for l in range(lmax + 1):
         c = rng.standard_normal(3)
         a = rng.uniform(0.5, 2.0, size=3)
-        v = sum(c[k] * r ** (l + 2 * k) * np.exp(-a[k] * r * r) for k in range(3))
+        v = cut * sum(c[k] * r ** (l + 2 * k) * np.exp(-a[k] * r * r) for k in range(3))
         s = np.abs(v).max()
         out[l] = v / s if s > 0 else v
     return out
@@ -176,3 +179,12 @@ def request_inputs(req: Request, radius: float = 3.0, n_r: int = 2000):
     r = radius * rng.uniform(size=(req.n, 1)) ** (1.0 / 3.0)
     pts = req.center[None, :] + d / nrm * r
     return np.ascontiguousarray(pts), radial_table(rng, req.lmax, n_r, radius)
+
+
+def upstream_gradient_device(nfun: int, n: int, seed: int, device):
+    """[nfun][n] N(0,1) upstream gradient drawn on the device with torch's seeded
+    generator (large batches, where a host draw would dominate set-up time)."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    return torch.randn((nfun, n), generator=g, dtype=torch.float64, device=device)

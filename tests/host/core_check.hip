@@ -14,3 +14,23 @@ static void run(long n, const T *u, T *out)
 extern "C" void core_eval9_f64(long n, const double *u, double *out) { run<9, double>(n, u, out); }
 extern "C" void core_eval9_f32(long n, const float *u, float *out) { run<9, float>(n, u, out); }
 extern "C" void core_eval3_f64(long n, const double *u, double *out) { run<3, double>(n, u, out); }
+
+#include "../../paper_2510_05282_amd/csrc/sh_dual.h"
+
+// Tangential gradient at unit vectors u (r = 1): g = v - u (u . v).
+template <int LMAX>
+static void grad(long n, const double *u, const double *G, double *out)
+{
+    for (long i = 0; i < n; ++i) {
+        double vx, vy, vz;
+        shk::grad_unit<LMAX>(u[3 * i], u[3 * i + 1], u[3 * i + 2],
+                             [&](int r) { return G[r * n + i]; }, vx, vy, vz);
+        const double uv = u[3 * i] * vx + u[3 * i + 1] * vy + u[3 * i + 2] * vz;
+        out[3 * i] = vx - u[3 * i] * uv;
+        out[3 * i + 1] = vy - u[3 * i + 1] * uv;
+        out[3 * i + 2] = vz - u[3 * i + 2] * uv;
+    }
+}
+
+extern "C" void core_grad9(long n, const double *u, const double *G, double *out) { grad<9>(n, u, G, out); }
+extern "C" void core_grad6(long n, const double *u, const double *G, double *out) { grad<6>(n, u, G, out); }

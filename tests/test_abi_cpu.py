@@ -53,3 +53,30 @@ def test_eval_argument_validation(L):
     # n == 0 is a no-op, even with NULL pointers
     assert L.sh_eval(9, 0, None, None, None) == 0
     assert L.sh_eval_f32(0, 0, None, None, None) == 0
+
+
+def test_grad_argument_validation(L):
+    fake = ctypes.c_void_p(0x1000)
+    assert L.sh_eval_grad(10, 5, fake, fake, fake, None) == 1
+    assert L.sh_eval_grad(3, -2, fake, fake, fake, None) == 1
+    assert L.sh_eval_grad(3, 5, fake, None, fake, None) == 1
+    assert L.sh_eval_grad(3, 5, fake, fake, None, None) == 1
+    assert L.sh_eval_grad(3, 0, None, None, None, None) == 0
+
+
+def test_radial_and_projector_validation(L):
+    fake = ctypes.c_void_p(0x1000)
+    h = ctypes.c_void_p()
+    vals = (ctypes.c_double * 8)()
+    # every rejected call returns before touching the device
+    assert L.sh_radial_create(10, 1, 4, ctypes.c_double(3.0), vals, ctypes.byref(h)) == 1
+    assert L.sh_radial_create(1, 0, 4, ctypes.c_double(3.0), vals, ctypes.byref(h)) == 1
+    assert L.sh_radial_create(1, 1, 1, ctypes.c_double(3.0), vals, ctypes.byref(h)) == 1
+    assert L.sh_radial_create(1, 1, 4, ctypes.c_double(0.0), vals, ctypes.byref(h)) == 1
+    assert L.sh_radial_create(1, 1, 4, ctypes.c_double(float("inf")), vals, ctypes.byref(h)) == 1
+    assert L.sh_radial_create(1, 1, 4, ctypes.c_double(3.0), None, ctypes.byref(h)) == 1
+    assert L.sh_radial_create(1, 1, 4, ctypes.c_double(3.0), vals, None) == 1
+    assert L.sh_radial_destroy(None) == 0
+    assert L.sh_projectors(3, 1, fake, fake, 10, fake, None, None, fake, None) == 1  # no radial
+    assert L.sh_projectors(-1, 1, fake, fake, 10, fake, fake, None, fake, None) == 1
+    assert L.sh_projectors_f32(3, -1, fake, fake, 10, fake, fake, None, fake, None) == 1

@@ -74,3 +74,19 @@ def test_core_fp32_matches_oracle(core, orc):
     ref = orc.eval_xyz(9, u)  # at the float unit vectors, widened exactly
     err = np.abs(got.astype(LD) - ref).max(axis=1)
     assert err.max() <= 5e-6, err.max()
+
+
+@pytest.mark.parametrize("lmax,fn", [(9, "core_grad9"), (6, "core_grad6")])
+def test_core_gradient_matches_oracle(core, orc, lmax, fn):
+    """Dual-number gradient of the factorised forms, projected on the tangent
+    plane, against the oracle's analytic gradient (unit points, r = 1)."""
+    getattr(core, fn).argtypes = [ctypes.c_long, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    u = _units(_pts(), np.float64)
+    F = (lmax + 1) ** 2
+    G = np.random.default_rng(41).standard_normal((F, u.shape[0]))
+    out = np.empty((u.shape[0], 3))
+    getattr(core, fn)(u.shape[0], u.ctypes.data, G.ctypes.data, out.ctypes.data)
+    ref = orc.grad_xyz(lmax, u, G)
+    scale = 1 + np.abs(ref).max(axis=1, keepdims=True)
+    err = (np.abs(out.astype(LD) - ref) / scale).max()
+    assert err <= 1e-12, err

@@ -1,0 +1,128 @@
+"""GPU parity of the backward kernel (sh_eval_grad) and the autograd op.
+
+Tolerances (per point, g the exact gradient): against the oracle's analytic
+gradient |dg|_inf <= 1e-12 (1 + |g|_inf); against central differences of the GPU
+forward with h = 1e-6, |dg|_inf <= 1e-7 (1 + |g|_inf)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2510_05282_amd as sh
+from paper_2510_05282_amd import workloads
+
+pytestmark = pytest.mark.gpu
+LD = np.longdouble
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _rel_err(got, ref):
+    scale = 1 + np.abs(ref.astype(np.float64)).max(axis=1)
+    return (np.abs(got.astype(LD) - ref).max(axis=1) / scale).max()
+
+
+def test_grad_parity_oracle(dev, orc):
+    lmax = 6
+    pts = np.concatenate([workloads.points_gradient(n=20000, seed=5),
+                          np.array([[0, 0, 2.0], [0, 0, -0.7], [1.5, 0, 0], [0, -2, 0],
+                                    [1e-9, 0, 1.0], [0, 0, 0.0]])])
+    G = np.random.default_rng(6).standard_normal((49, pts.shape[0]))
+    _say("case: grad parity lmax 6, n =", pts.shape[0])
+    x = torch.from_numpy(pts).to(dev)
+    g = sh.sh_eval_grad(lmax, x, torch.from_numpy(G).to(dev)).cpu().numpy()
+    ref = orc.grad_xyz(lmax, pts, G)
+    err = _rel_err(g, ref)
+    _say("  max relative err:", float(err))
+    assert err <= 1e-12
+    assert np.all(g[-1] == 0)  # the origin
+
+
+def test_grad_every_lmax(dev, orc):
+    pts = workloads.points_gradient(n=3000, seed=7)
+    x = torch.from_numpy(pts).to(dev)
+    for lmax in range(10):
+        _say("case: grad lmax", lmax)
+        F = (lmax + 1) ** 2
+        G = np.random.default_rng(lmax).standard_normal((F, pts.shape[0]))
+        g = sh.sh_eval_grad(lmax, x, torch.from_numpy(G).to(dev)).cpu().numpy()
+        assert _rel_err(g, orc.grad_xyz(lmax, pts, G)) <= 1e-12
+
+
+@pytest.mark.parametrize("n", [1, 63, 65, 257, 1000])
+def test_grad_ragged(dev, orc, n):
+    pts = workloads.points_gradient(n=n, seed=100 + n)
+    G = np.random.default_rng(n).standard_normal((100, n))
+    g = sh.sh_eval_grad(9, torch.from_numpy(pts).to(dev), torch.from_numpy(G).to(dev)).cpu().numpy()
+    assert _rel_err(g, orc.grad_xyz(9, pts, G)) <= 1e-12
+
+
+def _fd(dev, lmax, x, G, h=1e-6):
+    cols = []
+    for k in range(3):
+        e = torch.zeros(3, dtype=torch.float64, device=dev)
+        e[k] = h
+        yp = sh.sh_eval(lmax, (x + e).contiguous())
+        ym = sh.sh_eval(lmax, (x - e).contiguous())
+        cols.append(((yp - ym) * G).sum(0) / (2 * h))
+    return torch.stack(cols, 1)
+
+
+def test_grad_vs_central_differences(dev):
+    lmax = 6
+    pts = workloads.points_gradient(n=10000, seed=8)
+    x = torch.from_numpy(pts).to(dev)
+    G = torch.from_numpy(np.random.default_rng(9).standard_normal((49, 10000))).to(dev)
+    g = sh.sh_eval_grad(lmax, x, G)
+    fd = _fd(dev, lmax, x, G)
+    err = ((g - fd).abs().max(1).values / (1 + g.abs().max(1).values)).max().item()
+    _say("  fd max relative err:", err)
+    assert err <= 1e-7
+
+
+def test_grad_full_size_sampled(dev, orc):
+    """2^24 points (radius in [0.5, 5]), lmax 6: forward then backward with an
+    N(0,1) upstream gradient, in the shape the benchmark times; 10,000 sampled
+    points against the oracle's gradient and central differences."""
+    n, lmax = 1 << 24, 6
+    _say("case: grad full size, n =", n)
+    pts = workloads.points_gradient(n=n, seed=0)
+    x = torch.from_numpy(pts).to(dev)
+    y = sh.sh_eval(lmax, x)
+    G = workloads.upstream_gradient_device(49, n, seed=1, device=dev)
+    g = sh.sh_eval_grad(lmax, x, G)
+    idx = np.sort(np.random.default_rng(2).choice(n, 10000, replace=False))
+    it = torch.from_numpy(idx).to(dev)
+    gs = g[it].cpu().numpy()
+    Gs = G[:, it].contiguous()
+    err = _rel_err(gs, orc.grad_xyz(lmax, pts[idx], Gs.cpu().numpy()))
+    _say("  oracle max relative err:", float(err))
+    assert err <= 1e-12
+    fd = _fd(dev, lmax, x[it].contiguous(), Gs).cpu().numpy()
+    err_fd = (np.abs(gs - fd).max(1) / (1 + np.abs(gs).max(1))).max()
+    _say("  fd max relative err:", float(err_fd))
+    assert err_fd <= 1e-7
+    del y, G, g
+
+
+def test_autograd_function(dev):
+    pts = workloads.points_gradient(n=5000, seed=10)
+    x = torch.from_numpy(pts).to(dev).requires_grad_(True)
+    y = sh.spherical_harmonics(x, 5)
+    G = torch.from_numpy(np.random.default_rng(11).standard_normal((36, 5000))).to(dev)
+    (y * G).sum().backward()
+    ref = sh.sh_eval_grad(5, x.detach(), G)
+    assert torch.equal(x.grad, ref)
+    small = torch.from_numpy(pts[:6]).to(dev).requires_grad_(True)
+    assert torch.autograd.gradcheck(lambda t: sh.spherical_harmonics(t, 4), (small,), eps=1e-6,
+                                    atol=1e-7, rtol=1e-6)

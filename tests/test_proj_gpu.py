@@ -1,0 +1,105 @@
+"""GPU parity of the fused projector build against the oracle.
+
+Tolerance: 1e-13 * max(1, max|R_l|) in FP64 and 5e-6 * max(1, max|R_l|) in FP32;
+the synthetic radial tables are scaled to max|R_l| = 1."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2510_05282_amd as sh
+from paper_2510_05282_amd import workloads
+
+pytestmark = pytest.mark.gpu
+LD = np.longdouble
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _run(dev, lmax, A, dtype=torch.float64, tables=None, table_of_atom=None):
+    tables = A.tables if tables is None else tables
+    rad = sh.Radial(tables, A.r_max)
+    fn = sh.sh_projectors if dtype == torch.float64 else sh.sh_projectors_f32
+    toa = None if table_of_atom is None else torch.from_numpy(table_of_atom.astype(np.int32)).to(dev)
+    out = fn(lmax, torch.from_numpy(A.centers).to(dev, dtype), torch.from_numpy(A.offsets).to(dev),
+             torch.from_numpy(A.points).to(dev, dtype), rad, table_of_atom=toa)
+    torch.cuda.synchronize()
+    rad.close()
+    return out.cpu().numpy()
+
+
+def test_projectors_64_atoms_fp64(dev, orc):
+    """64 atoms in a 20^3 box, spheres of radius 3 on a 0.2 grid, lmax 3,
+    2000-knot radial tables: the whole output against the oracle."""
+    A = workloads.atom_spheres(seed=0)
+    _say("case: projectors 64 atoms, n_points =", int(A.offsets[-1]))
+    got = _run(dev, 3, A)
+    ref = orc.projectors(3, A.centers, A.offsets, A.points, A.tables, A.r_max)
+    err = float(np.abs(got.astype(LD) - ref).max())
+    _say("  max abs err:", err)
+    assert err <= 1e-13
+
+
+def test_projectors_fp32(dev, orc):
+    A = workloads.atom_spheres(seed=1, n_atoms=16)
+    A.points = A.points.astype(np.float32).astype(np.float64)  # the oracle sees the float inputs
+    A.centers = A.centers.astype(np.float32).astype(np.float64)
+    _say("case: projectors fp32, n_points =", int(A.offsets[-1]))
+    got = _run(dev, 3, A, torch.float32)
+    ref = orc.projectors(3, A.centers, A.offsets, A.points, A.tables, A.r_max)
+    err = float(np.abs(got.astype(LD) - ref).max())
+    _say("  max abs err:", err)
+    assert err <= 5e-6
+
+
+@pytest.mark.parametrize("lmax", list(range(10)))
+def test_projectors_every_lmax(dev, orc, lmax):
+    A = workloads.atom_spheres(seed=2, n_atoms=3, radius=1.5, h=0.25, lmax=lmax, n_r=300)
+    got = _run(dev, lmax, A)
+    ref = orc.projectors(lmax, A.centers, A.offsets, A.points, A.tables, A.r_max)
+    assert np.abs(got.astype(LD) - ref).max() <= 1e-13
+
+
+def test_unit_radial_is_plain_eval(dev):
+    A = workloads.atom_spheres(seed=3, n_atoms=4, radius=1.0, h=0.2, lmax=9, n_r=64)
+    got = _run(dev, 9, A, tables=np.ones_like(A.tables))
+    for a in range(4):
+        j0, j1 = int(A.offsets[a]), int(A.offsets[a + 1])
+        d = torch.from_numpy(A.points[j0:j1] - A.centers[a]).to(dev)
+        ref = sh.sh_eval(9, d).cpu().numpy()
+        assert np.abs(got[100 * j0:100 * j1].reshape(100, j1 - j0) - ref).max() <= 1e-15
+
+
+def test_shared_tables_and_empty_atoms(dev, orc):
+    """Atoms pick tables through table_of_atom; atoms with no points write nothing."""
+    A = workloads.atom_spheres(seed=4, n_atoms=5, radius=1.2, h=0.3, lmax=2, n_r=200)
+    # make atoms 1 and 3 empty
+    keep = []
+    offs = [0]
+    for a in range(5):
+        j0, j1 = int(A.offsets[a]), int(A.offsets[a + 1])
+        if a not in (1, 3):
+            keep.append(A.points[j0:j1])
+        offs.append(offs[-1] + (0 if a in (1, 3) else j1 - j0))
+    A.points = np.concatenate(keep)
+    A.offsets = np.array(offs, dtype=np.int64)
+    tables = A.tables[:2]
+    toa = np.array([1, 0, 1, 1, 0])
+    got = _run(dev, 2, A, tables=tables, table_of_atom=toa)
+    ref = orc.projectors(2, A.centers, A.offsets, A.points, tables, A.r_max, table_of_atom=toa)
+    assert np.abs(got.astype(LD) - ref).max() <= 1e-13
+
+
+def test_projectors_deterministic(dev):
+    A = workloads.atom_spheres(seed=5, n_atoms=8)
+    assert np.array_equal(_run(dev, 3, A), _run(dev, 3, A))
