@@ -33,6 +33,7 @@ def _parse():
                     help="points of the oracle's CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="headline only")
+    ap.add_argument("--serve-requests", type=int, default=10_000)
     return ap.parse_args()
 
 
@@ -85,6 +86,107 @@ def write_probe(buf, steps):
     total, per = time_launches(lambda: buf.fill_(1.0), steps, 2)
     avg = sum(per) / len(per)
     return {"bytes": buf.numel() * buf.element_size(), "gbs": buf.numel() * buf.element_size() / avg / 1e9}
+
+
+def bench_projectors(sh, workloads, dev, steps):
+    """64 atoms, spheres of radius 3 on a 0.2 grid, lmax 3, 2000-knot tables."""
+    import torch
+    A = workloads.atom_spheres(seed=0)
+    rad = sh.Radial(A.tables, A.r_max)
+    c = torch.from_numpy(A.centers).to(dev)
+    off = torch.from_numpy(A.offsets).to(dev)
+    p = torch.from_numpy(A.points).to(dev)
+    n = int(A.offsets[-1])
+    out = torch.empty(16 * n, dtype=torch.float64, device=dev)
+    total, per = time_launches(lambda: sh.sh_projectors(3, c, off, p, rad, out=out), steps, 3)
+    avg = sum(per) / len(per)
+    bpp = 16 * 8 + 24
+    rad.close()
+    return {"workload": "64 atoms, r=3 spheres on a 0.2 grid, lmax 3, FP64", "n_points": n,
+            "ms_per_build": avg * 1e3, "points_per_s": n / avg, "gbs": n * bpp / avg / 1e9,
+            "frac": n * bpp / avg / 1e9 / HBM_PEAK_GBS, "bytes_per_point": bpp}
+
+
+def bench_gradient(sh, workloads, dev, steps):
+    """2^24 points (radius in [0.5, 5]), lmax 6: forward, then backward with an
+    N(0,1) upstream gradient."""
+    import torch
+    n, lmax = 1 << 24, 6
+    x = torch.from_numpy(workloads.points_gradient(n=n, seed=0)).to(dev)
+    y = torch.empty((49, n), dtype=torch.float64, device=dev)
+    G = workloads.upstream_gradient_device(49, n, seed=1, device=dev)
+    g = torch.empty((n, 3), dtype=torch.float64, device=dev)
+    _, per_f = time_launches(lambda: sh.sh_eval(lmax, x, out=y), steps, 2)
+    _, per_b = time_launches(lambda: sh.sh_eval_grad(lmax, x, G, grad_xyz=g), steps, 2)
+    f, b = sum(per_f) / len(per_f), sum(per_b) / len(per_b)
+    bf, bb = 24 + 49 * 8, 24 + 49 * 8 + 24
+    return {"workload": "2^24 points, lmax 6, FP64, forward + backward", "n_points": n,
+            "forward_ms": f * 1e3, "backward_ms": b * 1e3,
+            "forward_points_per_s": n / f, "backward_points_per_s": n / b,
+            "forward_gbs": n * bf / f / 1e9, "backward_gbs": n * bb / b / 1e9,
+            "backward_frac": n * bb / b / 1e9 / HBM_PEAK_GBS, "backward_bytes_per_point": bb}
+
+
+def bench_serving(sh, workloads, dev, n_req):
+    """n_req projector requests (lmax ~ U{0..9}, n log-uniform in [1e3, 1e6], 80%
+    FP64), per-atom points and radial tables resident on the device, 64 GB budget.
+    First a closed loop (everything submitted at once) gives the saturation rate;
+    then Poisson arrivals at 0.7x that rate give the latencies."""
+    import numpy as np
+    import torch
+    from paper_2510_05282_amd.serve import SH_REQ_AUTORELEASE, Server
+    reqs = workloads.request_stream(n_req=n_req, rate=1.0, seed=0)
+    tabs = np.zeros((n_req, 10, 2000))
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(7)
+    pts = []
+    for k, r in enumerate(reqs):
+        rng = np.random.default_rng(r.seed)
+        tabs[k, : r.lmax + 1] = workloads.radial_table(rng, r.lmax, 2000, 3.0)
+        dt = torch.float64 if r.dtype == "f64" else torch.float32
+        d = torch.randn((r.n, 3), generator=gen, dtype=torch.float64, device=dev)
+        d = d / d.norm(dim=1, keepdim=True)
+        rr = 3.0 * torch.rand((r.n, 1), generator=gen, dtype=torch.float64, device=dev) ** (1 / 3)
+        pts.append((torch.from_numpy(r.center).to(dev) + d * rr).to(dt).contiguous())
+    radial = sh.Radial(tabs, 3.0)
+    total_points = sum(r.n for r in reqs)
+    total_bytes = sum((r.lmax + 1) ** 2 * r.n * (8 if r.dtype == "f64" else 4) for r in reqs)
+    out = {"workload": f"{n_req} projector requests, lmax U{{0..9}}, n log-U[1e3,1e6], 80% FP64, "
+                       "64 GB budget, 3 streams",
+           "total_points": total_points, "output_bytes": total_bytes}
+
+    def run(arrivals):
+        srv = Server(64 << 30, max_pending=n_req + 1, n_slots=3)
+        atoms = [srv.add_atom(p, r.center, radial, table=k) for k, (p, r) in enumerate(zip(pts, reqs))]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for a, r, ta in zip(atoms, reqs, arrivals):
+            while time.perf_counter() - t0 < ta:
+                pass
+            srv.submit(a, r.lmax, SH_REQ_AUTORELEASE)
+        srv.drain(600)
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        lat = srv.latencies_ms()
+        srv.close()
+        return wall, st, lat
+
+    wall, st, lat = run([0.0] * n_req)
+    rate = n_req / wall
+    out["closed_loop"] = {"wall_s": wall, "req_per_s": rate, "points_per_s": total_points / wall,
+                          "gbs": total_bytes / wall / 1e9, "batches": st["batches"],
+                          "deferred": st["deferred"], "peak_bytes": st["peak_bytes"]}
+    lam = 0.7 * rate
+    arr = workloads.request_stream(n_req=n_req, rate=lam, seed=0)
+    wall, st, lat = run([r.arrival for r in arr])
+    span = st["last_done_s"] - st["first_submit_s"]
+    out["poisson"] = {"rate_req_per_s": lam, "p50_ms": float(np.percentile(lat, 50)),
+                      "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
+                      "points_per_s": total_points / span, "gbs": total_bytes / span / 1e9,
+                      "batches": st["batches"], "deferred": st["deferred"], "peak_bytes": st["peak_bytes"],
+                      "completed": st["completed"], "failed": st["failed"]}
+    radial.close()
+    return out
 
 
 def cpu_baseline(pts, lmax, sample):
@@ -144,7 +246,7 @@ def main():
                    "n_points": n, "lmax": 9},
         "roofline": {"bound": "hbm", "achieved": head["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": head["frac"], "traffic": None,
-                     "kernel": "fwd_kernel<9,double>", "kernel_ms": head["kernel_ms"],
+                     "kernel": "shk::fwd_kernel<9,double,2>", "kernel_ms": head["kernel_ms"],
                      "bytes_per_point": head["bytes_per_point"]},
     }
 
@@ -165,6 +267,19 @@ def main():
 
     del out
     torch.cuda.empty_cache()
+    if not args.no_extras:
+        _log("projectors")
+        result["projectors"] = bench_projectors(sh, workloads, dev, 20)
+        _log("  ", json.dumps(result["projectors"]))
+        _log("gradient")
+        result["gradient"] = bench_gradient(sh, workloads, dev, max(5, args.steps // 2))
+        _log("  ", json.dumps(result["gradient"]))
+        torch.cuda.empty_cache()
+        _log("serving")
+        result["serving"] = bench_serving(sh, workloads, dev, args.serve_requests)
+        _log("  ", json.dumps(result["serving"]))
+        torch.cuda.empty_cache()
+
     if not args.no_cpu_baseline:
         _log("cpu baseline")
         result["cpu_baseline"] = cpu_baseline(pts, 9, args.cpu_sample)

@@ -1,17 +1,21 @@
-// sh_eval.hip -- forward kernels: all real Y_lm, l <= lmax, for a batch of points.
+// sh_eval.hip -- launchers of the forward kernels (all real Y_lm, l <= lmax).
 //
-// One thread per point.  Each thread loads its point, normalises it in FP64
-// (hardware rsqrt refined by Newton steps, with the near-origin guard), evaluates
-// the factorised formulas and writes every (l, m) value to its own row of the
-// [F][ld] output.  The 64 lanes of a wave hold 64 consecutive points, so each
-// row store of a wave is one contiguous, line-aligned 512 B (FP64) or 256 B
-// (FP32) run.  Output is written exactly once and never read back, so the stores
-// are non-temporal.  The path moves 3s + F s bytes per point (s = element size)
-// against a few hundred flops: it is bound by HBM stores, not by arithmetic.
+// The kernel (sh_fwd.h) normalises each point in FP64, evaluates the factorised
+// formulas and writes every (l, m) value to its row of the [F][ld] output.  The
+// path moves 3s + F s bytes per point (s = element size) against a few hundred
+// flops, so it is bound by HBM stores.  Launch choices, all measured on MI355X:
+//  - FP64 evaluates two adjacent points per lane and stores 16 bytes per row
+//    (one contiguous 1 KiB run per wave and row); FP32 one point per lane.
+//    Outputs whose rows are not 16-byte aligned take the one-point kernel.
+//  - Workgroups are remapped so each XCD walks one contiguous range of points.
+//  - Each workgroup reserves LDS it does not use, which caps the resident
+//    workgroups per CU (2 for FP64, 3 for FP32 at lmax >= 6).  Fewer points in
+//    flight keep the concurrent writes of each row in a smaller window, which the
+//    HBM write path turns into a few percent more bandwidth.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "sh_core.h"
+#include "sh_fwd.h"
 #include "sh_internal.h"
 
 namespace shk {
@@ -19,33 +23,40 @@ namespace shk {
 // Points per launch: keeps every per-row byte offset of a launch below 2^31 so
 // the store address is a scalar row base plus a 32-bit per-lane offset.
 constexpr int64_t kChunk = int64_t(1) << 28;
-constexpr int kBlock = 256;
 
-template <int LMAX, typename TIO>
-__global__ __launch_bounds__(kBlock) void fwd_kernel(const TIO* __restrict__ xyz, TIO* __restrict__ out,
-                                                     uint32_t n, int64_t ld)
+template <typename TIO>
+static size_t occupancy_lds(int lmax)
 {
-    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const TIO* p = xyz + 3 * size_t(i);
-    double xb, yb, zb, keep;
-    normalize(double(p[0]), double(p[1]), double(p[2]), xb, yb, zb, keep);
-    const uint32_t boff = i * uint32_t(sizeof(TIO));
-    eval_unit<LMAX, TIO>(TIO(xb), TIO(yb), TIO(zb), TIO(keep), [&](int r, TIO v) {
-        TIO* dst = reinterpret_cast<TIO*>(reinterpret_cast<char*>(out + int64_t(r) * ld) + boff);
-        __builtin_nontemporal_store(v, dst);
-    });
+    if (lmax < 6) return 0;
+    return sizeof(TIO) == 8 ? 54 * 1024 : 40 * 1024;
+}
+
+template <int LMAX, typename TIO, int PPL>
+static hipError_t launch_one(const TIO* xyz, TIO* out, int64_t n, int64_t ld, hipStream_t s)
+{
+    const int64_t nvec = n / PPL;
+    const unsigned grid = unsigned((nvec + kFwdBlock - 1) / kFwdBlock);
+    hipLaunchKernelGGL((fwd_kernel<LMAX, TIO, PPL>), dim3(grid), dim3(kFwdBlock), occupancy_lds<TIO>(LMAX), s,
+                       xyz, out, uint32_t(n), ld);
+    return hipGetLastError();
 }
 
 template <int LMAX, typename TIO>
 static hipError_t launch_fwd_l(int64_t n, const TIO* xyz, TIO* out, int64_t ld, hipStream_t s)
 {
+    constexpr int kVec = sizeof(TIO) == 8 ? 2 : 1;
+    const bool vec_ok = kVec > 1 && ld % kVec == 0 && reinterpret_cast<uintptr_t>(out) % (kVec * sizeof(TIO)) == 0;
     for (int64_t c0 = 0; c0 < n; c0 += kChunk) {
         const int64_t nc = n - c0 < kChunk ? n - c0 : kChunk;
-        const unsigned grid = unsigned((nc + kBlock - 1) / kBlock);
-        hipLaunchKernelGGL((fwd_kernel<LMAX, TIO>), dim3(grid), dim3(kBlock), 0, s, xyz + 3 * c0, out + c0,
-                           uint32_t(nc), ld);
-        hipError_t e = hipGetLastError();
+        hipError_t e;
+        if (vec_ok) {
+            const int64_t nmain = nc - nc % kVec;
+            e = nmain ? launch_one<LMAX, TIO, kVec>(xyz + 3 * c0, out + c0, nmain, ld, s) : hipSuccess;
+            if (e == hipSuccess && nmain < nc)
+                e = launch_one<LMAX, TIO, 1>(xyz + 3 * (c0 + nmain), out + c0 + nmain, nc - nmain, ld, s);
+        } else {
+            e = launch_one<LMAX, TIO, 1>(xyz + 3 * c0, out + c0, nc, ld, s);
+        }
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -1,0 +1,73 @@
+// sh_fwd.h -- the forward kernel template (all real Y_lm of a batch of points).
+//
+// Each lane evaluates PPL adjacent points at once (the formula core runs on a
+// PPL-wide clang vector), so every (l, m) row gets one PPL * sizeof(T) byte
+// store per lane and one contiguous 64 * PPL * sizeof(T) byte run per wave.
+// Points are normalised in FP64 whatever the output type.
+//
+// Work distribution is XCD-aware: the hardware deals consecutive workgroups
+// round-robin to the 8 XCDs, so workgroup b is remapped to the logical tile
+// start(b % 8) + b / 8, giving each XCD one contiguous range of points.  The
+// points that are being written at any moment then stay within a few compact
+// windows of every output row, which the HBM write path rewards measurably.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sh_core.h"
+
+namespace shk {
+
+constexpr int kFwdBlock = 256;
+constexpr int kXcds = 8;
+
+template <typename S, int N> struct vec_of { typedef S type __attribute__((ext_vector_type(N))); };
+template <typename S> struct vec_of<S, 1> { typedef S type; };
+
+// Logical workgroup of hardware workgroup b in a grid of G: a bijection on
+// [0, G) that makes the workgroups dispatched to each XCD contiguous.
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t G)
+{
+    const uint32_t q = G / kXcds, r = G % kXcds, x = b % kXcds;
+    return x * q + (x < r ? x : r) + b / kXcds;
+}
+
+template <typename V, int PPL>
+__device__ __forceinline__ auto& lane(V& v, int k)
+{
+    if constexpr (PPL == 1) return v;
+    else return reinterpret_cast<scalar_t<V>*>(&v)[k];
+}
+
+// out is [F][ld], xyz is [n][3]; n * sizeof(TIO) < 2^31 so per-row byte offsets
+// fit 32 bits (the host splits larger batches).  With PPL > 1 the host
+// guarantees n % PPL == 0, ld % PPL == 0 and a PPL * sizeof(TIO)-aligned out
+// (a remainder of fewer than PPL points goes to a PPL = 1 launch).
+template <int LMAX, typename TIO, int PPL>
+__global__ __launch_bounds__(kFwdBlock) void fwd_kernel(const TIO* __restrict__ xyz, TIO* __restrict__ out,
+                                                        uint32_t n, int64_t ld)
+{
+    using V = typename vec_of<TIO, PPL>::type;
+    const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t t = b * kFwdBlock + threadIdx.x;  // vector index
+    const uint32_t i0 = t * PPL;                     // first point of this lane
+    if (i0 >= n) return;
+    V x, y, z, k;
+#pragma unroll
+    for (int q = 0; q < PPL; ++q) {
+        const TIO* p = xyz + 3 * size_t(i0 + q);
+        double xb, yb, zb, kb;
+        normalize(double(p[0]), double(p[1]), double(p[2]), xb, yb, zb, kb);
+        lane<V, PPL>(x, q) = TIO(xb);
+        lane<V, PPL>(y, q) = TIO(yb);
+        lane<V, PPL>(z, q) = TIO(zb);
+        lane<V, PPL>(k, q) = TIO(kb);
+    }
+    const uint32_t boff = i0 * uint32_t(sizeof(TIO));
+    eval_unit<LMAX, V>(x, y, z, k, [&](int r, V v) {
+        *reinterpret_cast<V*>(reinterpret_cast<char*>(out + int64_t(r) * ld) + boff) = v;
+    });
+}
+
+}  // namespace shk

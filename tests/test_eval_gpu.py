@@ -105,6 +105,21 @@ def test_padded_rows_ld(dev, orc):
         assert np.abs(b[:, :n].astype(LD) - ref).max() <= tol
 
 
+def test_misaligned_output_rows(dev, orc):
+    """Rows that are not 16-byte aligned take the one-point-per-lane kernel."""
+    n, ld = 999, 1000
+    pts = workloads.isotropic_points(n, 0.1, 5.0, seed=17)
+    x = torch.from_numpy(pts).to(dev)
+    buf = torch.full((100 * ld + 1,), -3.0, dtype=torch.float64, device=dev)
+    view = buf[1:].view(100, ld)[:, :n]
+    sh.sh_eval_ld(9, x, view)
+    b = buf.cpu().numpy()
+    assert b[0] == -3.0
+    rows = b[1:].reshape(100, ld)
+    assert np.all(rows[:, n:] == -3.0)
+    assert np.abs(rows[:, :n].astype(LD) - orc.eval_xyz(9, pts)).max() <= TOL64
+
+
 def test_fp32_parity_per_l(dev, orc):
     pts = workloads.points_plain_eval(seed=0).astype(np.float32)
     _say("case: plain eval fp32, n =", pts.shape[0])

@@ -1,0 +1,132 @@
+"""The projector server on the GPU: every request's result is the same alone and
+in a mixed stream (same kernel code for its lmax and dtype: bitwise), and
+matches the oracle."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2510_05282_amd as sh
+from paper_2510_05282_amd import workloads
+from paper_2510_05282_amd.serve import DONE, SH_REQ_AUTORELEASE, Server
+
+pytestmark = pytest.mark.gpu
+LD = np.longdouble
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _requests(dev, n_req, seed, n_hi=1e5):
+    reqs = workloads.request_stream(n_req=n_req, seed=seed, n_hi=n_hi)
+    pts, tabs = [], []
+    for r in reqs:
+        p, t = workloads.request_inputs(r)
+        pts.append(p)
+        full = np.zeros((10, t.shape[1]))
+        full[: t.shape[0]] = t
+        tabs.append(full)
+    return reqs, pts, np.stack(tabs)
+
+
+def _setup(dev, server, reqs, pts, radial):
+    atoms, dev_pts = [], []
+    for k, (r, p) in enumerate(zip(reqs, pts)):
+        dt = torch.float64 if r.dtype == "f64" else torch.float32
+        t = torch.from_numpy(p).to(dev, dt).contiguous()
+        dev_pts.append(t)
+        atoms.append(server.add_atom(t, r.center, radial, table=k))
+    return atoms, dev_pts
+
+
+def test_alone_vs_mixed_and_oracle(dev, orc):
+    reqs, pts, tabs = _requests(dev, 48, seed=3)
+    radial = sh.Radial(tabs, 3.0)
+    srv = Server(4 << 30, n_slots=3)
+    atoms, _ = _setup(dev, srv, reqs, pts, radial)
+    _say("case: server alone vs mixed,", len(reqs), "requests")
+    alone = []
+    for a, r in zip(atoms, reqs):
+        t = srv.submit(a, r.lmax)
+        assert srv.wait(t, 60) == DONE
+        dt = torch.float64 if r.dtype == "f64" else torch.float32
+        alone.append(srv.result(t, r.lmax, r.n, dt).clone())
+        srv.release(t)
+    tickets = [srv.submit(a, r.lmax) for a, r in zip(atoms, reqs)]
+    for t in tickets:
+        assert srv.wait(t, 60) == DONE
+    st = srv.stats()
+    _say("  batches:", st["batches"], "completed:", st["completed"])
+    for k, (t, r) in enumerate(zip(tickets, reqs)):
+        dt = torch.float64 if r.dtype == "f64" else torch.float32
+        mixed = srv.result(t, r.lmax, r.n, dt)
+        assert torch.equal(mixed, alone[k]), k
+        srv.release(t)
+    # a sample of requests against the oracle
+    for k in range(0, len(reqs), 6):
+        r = reqs[k]
+        p = pts[k] if r.dtype == "f64" else pts[k].astype(np.float32).astype(np.float64)
+        c = np.asarray(r.center)[None]
+        ref = orc.projectors(r.lmax, c, np.array([0, r.n]), p, tabs[k][None, : r.lmax + 1], 3.0)
+        tol = 1e-13 if r.dtype == "f64" else 5e-6
+        err = float(np.abs(alone[k].cpu().numpy().ravel().astype(LD) - ref).max())
+        assert err <= tol, (k, r.lmax, r.dtype, err)
+    srv.close()
+    radial.close()
+
+
+def test_small_budget_defers_and_completes(dev, orc):
+    """A 64 MiB budget with requests of up to about 40 MB: admission waits for
+    memory, everything completes, results still match the oracle."""
+    reqs, pts, tabs = _requests(dev, 24, seed=4, n_hi=6e5)
+    radial = sh.Radial(tabs, 3.0)
+    budget = 64 << 20
+    srv = Server(budget, n_slots=2)
+    atoms, _ = _setup(dev, srv, reqs, pts, radial)
+    fits = [k for k, r in enumerate(reqs)
+            if (r.lmax + 1) ** 2 * r.n * (8 if r.dtype == "f64" else 4) <= budget]
+    tickets = {k: srv.submit(atoms[k], reqs[k].lmax) for k in fits}
+    done = {}
+    for k, t in tickets.items():  # results are consumed (and released) in order
+        assert srv.wait(t, 120) == DONE
+        r = reqs[k]
+        dt = torch.float64 if r.dtype == "f64" else torch.float32
+        done[k] = srv.result(t, r.lmax, r.n, dt).cpu().numpy()
+        srv.release(t)
+    st = srv.stats()
+    _say("  deferred:", st["deferred"], "peak bytes:", st["peak_bytes"])
+    assert st["completed"] == len(fits) and st["peak_bytes"] <= budget and st["deferred"] > 0
+    for k in fits[:6]:
+        r = reqs[k]
+        p = pts[k] if r.dtype == "f64" else pts[k].astype(np.float32).astype(np.float64)
+        ref = orc.projectors(r.lmax, np.asarray(r.center)[None], np.array([0, r.n]), p,
+                             tabs[k][None, : r.lmax + 1], 3.0)
+        tol = 1e-13 if r.dtype == "f64" else 5e-6
+        assert float(np.abs(done[k].ravel().astype(LD) - ref).max()) <= tol
+    srv.close()
+    radial.close()
+
+
+def test_autorelease_stream(dev):
+    reqs, pts, tabs = _requests(dev, 200, seed=5, n_hi=2e4)
+    radial = sh.Radial(tabs, 3.0)
+    srv = Server(1 << 30, n_slots=3)
+    atoms, _ = _setup(dev, srv, reqs, pts, radial)
+    for a, r in zip(atoms, reqs):
+        srv.submit(a, r.lmax, SH_REQ_AUTORELEASE)
+    srv.drain(120)
+    st = srv.stats()
+    assert st["completed"] == 200 and st["failed"] == 0 and st["bytes_in_use"] == 0
+    lat = srv.latencies_ms()
+    _say("  p50/p99 ms:", float(np.percentile(lat, 50)), float(np.percentile(lat, 99)))
+    srv.close()
+    radial.close()
