@@ -34,6 +34,8 @@ def _parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="headline only")
     ap.add_argument("--serve-requests", type=int, default=10_000)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after the headline, copy 4 GiB once (calibrates HBM traffic counters)")
     return ap.parse_args()
 
 
@@ -229,6 +231,13 @@ def main():
     _log("headline: lmax 9 fp64")
     head = bench_forward(sh, xyz, out, 9, args.steps, args.warmup)
     _log("  ", json.dumps(head))
+    if args.copy_probe:
+        src = torch.ones(1 << 29, dtype=torch.float64, device=dev)  # 4 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        _log("copy probe: 4 GiB read + 4 GiB written by one copy kernel")
+        del src, dst
     result = {
         "metric": "Y_lm points/s (lmax=9, FP64, SoA output) + % HBM peak",
         "value": head["points_per_s"],
@@ -246,7 +255,7 @@ def main():
                    "n_points": n, "lmax": 9},
         "roofline": {"bound": "hbm", "achieved": head["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": head["frac"], "traffic": None,
-                     "kernel": "shk::fwd_kernel<9,double,2>", "kernel_ms": head["kernel_ms"],
+                     "kernel": "shk::fwd_kernel<9, double, 2>", "kernel_ms": head["kernel_ms"],
                      "bytes_per_point": head["bytes_per_point"]},
     }
 

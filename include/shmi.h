@@ -165,12 +165,13 @@ typedef struct {
  * batches in flight (1..16, one stream each). */
 int sh_server_create(uint64_t budget_bytes, int max_pending, int n_slots, sh_server_t *out);
 
-/* The same scheduler with a simulated executor that computes nothing: a batch
- * completes after its output bytes at bytes_per_second, and every fail_every-th
- * launch (0: never) fails.  For testing the scheduling logic without a GPU;
- * results are not readable (their addresses are arena offsets). */
+/* The same scheduler with a simulated executor that computes nothing: a launch
+ * takes launch_seconds of host time (0 to 10), a batch completes after its output
+ * bytes at bytes_per_second, and every fail_every-th launch (0: never) fails.
+ * For testing the scheduling logic without a GPU; results are not readable
+ * (their addresses are arena offsets). */
 int sh_server_create_simulated(uint64_t budget_bytes, int max_pending, int n_slots, double bytes_per_second,
-                               int fail_every, sh_server_t *out);
+                               int fail_every, double launch_seconds, sh_server_t *out);
 
 /* Refuses new work, fails what was not launched, waits for running batches,
  * then frees everything (NULL is a no-op). */

@@ -65,7 +65,7 @@ def lib() -> ctypes.CDLL:
     L.sh_projectors_f32.restype = i32
     u64, f64 = ctypes.c_uint64, ctypes.c_double
     L.sh_server_create.argtypes = [u64, i32, i32, ctypes.POINTER(vp)]
-    L.sh_server_create_simulated.argtypes = [u64, i32, i32, f64, i32, ctypes.POINTER(vp)]
+    L.sh_server_create_simulated.argtypes = [u64, i32, i32, f64, i32, f64, ctypes.POINTER(vp)]
     L.sh_server_destroy.argtypes = [vp]
     L.sh_server_add_atom.argtypes = [vp, i32, i64, vp, ctypes.POINTER(f64), vp, i32,
                                      ctypes.POINTER(i32)]

@@ -189,13 +189,14 @@ int sh_server_create(uint64_t budget_bytes, int max_pending, int n_slots, sh_ser
 }
 
 int sh_server_create_simulated(uint64_t budget_bytes, int max_pending, int n_slots, double bytes_per_second,
-                               int fail_every, sh_server_t *out)
+                               int fail_every, double launch_seconds, sh_server_t *out)
 {
     if (!out) return SH_EINVAL;
     *out = nullptr;
-    if (budget_bytes < 256 || max_pending < 1 || n_slots < 1 || n_slots > 16 || !(bytes_per_second > 0.0))
+    if (budget_bytes < 256 || max_pending < 1 || n_slots < 1 || n_slots > 16 || !(bytes_per_second > 0.0) ||
+        !(launch_seconds >= 0.0 && launch_seconds < 10.0))
         return SH_EINVAL;
-    return server_new(shs::make_sim_executor(budget_bytes, n_slots, bytes_per_second, fail_every), budget_bytes,
+    return server_new(shs::make_sim_executor(n_slots, bytes_per_second, fail_every, launch_seconds), budget_bytes,
                       max_pending, true, out);
 }
 

@@ -4,14 +4,15 @@
 // formulas and writes every (l, m) value to its row of the [F][ld] output.  The
 // path moves 3s + F s bytes per point (s = element size) against a few hundred
 // flops, so it is bound by HBM stores.  Launch choices, all measured on MI355X:
-//  - FP64 evaluates two adjacent points per lane and stores 16 bytes per row
-//    (one contiguous 1 KiB run per wave and row); FP32 one point per lane.
-//    Outputs whose rows are not 16-byte aligned take the one-point kernel.
+//  - Each lane evaluates 16 bytes' worth of adjacent points (two in FP64, four
+//    in FP32) and stores 16 bytes per row: one contiguous 1 KiB run per wave and
+//    row.  Outputs whose rows are not 16-byte aligned take the one-point kernel.
 //  - Workgroups are remapped so each XCD walks one contiguous range of points.
-//  - Each workgroup reserves LDS it does not use, which caps the resident
-//    workgroups per CU (2 for FP64, 3 for FP32 at lmax >= 6).  Fewer points in
-//    flight keep the concurrent writes of each row in a smaller window, which the
-//    HBM write path turns into a few percent more bandwidth.
+//  - The 16-byte kernels reserve LDS they do not use, which caps the resident
+//    workgroups per CU at 2 (8 waves).  Fewer points in flight keep the
+//    concurrent writes of each row in a smaller window, which the HBM write path
+//    turns into 3-14% more bandwidth depending on lmax; the one-point kernel
+//    runs uncapped (with 4-byte stores it needs the extra waves).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -24,19 +25,16 @@ namespace shk {
 // the store address is a scalar row base plus a 32-bit per-lane offset.
 constexpr int64_t kChunk = int64_t(1) << 28;
 
-template <typename TIO>
-static size_t occupancy_lds(int lmax)
-{
-    if (lmax < 6) return 0;
-    return sizeof(TIO) == 8 ? 54 * 1024 : 40 * 1024;
-}
+// LDS reserved (not used) per 256-thread workgroup of the 16-byte kernels: more
+// than a third of the CU's 160 KiB, so at most 2 workgroups are resident per CU.
+constexpr size_t kCapLds = 54 * 1024;
 
 template <int LMAX, typename TIO, int PPL>
 static hipError_t launch_one(const TIO* xyz, TIO* out, int64_t n, int64_t ld, hipStream_t s)
 {
     const int64_t nvec = n / PPL;
     const unsigned grid = unsigned((nvec + kFwdBlock - 1) / kFwdBlock);
-    hipLaunchKernelGGL((fwd_kernel<LMAX, TIO, PPL>), dim3(grid), dim3(kFwdBlock), occupancy_lds<TIO>(LMAX), s,
+    hipLaunchKernelGGL((fwd_kernel<LMAX, TIO, PPL>), dim3(grid), dim3(kFwdBlock), PPL > 1 ? kCapLds : 0, s,
                        xyz, out, uint32_t(n), ld);
     return hipGetLastError();
 }
@@ -44,7 +42,7 @@ static hipError_t launch_one(const TIO* xyz, TIO* out, int64_t n, int64_t ld, hi
 template <int LMAX, typename TIO>
 static hipError_t launch_fwd_l(int64_t n, const TIO* xyz, TIO* out, int64_t ld, hipStream_t s)
 {
-    constexpr int kVec = sizeof(TIO) == 8 ? 2 : 1;
+    constexpr int kVec = 16 / sizeof(TIO);
     const bool vec_ok = kVec > 1 && ld % kVec == 0 && reinterpret_cast<uintptr_t>(out) % (kVec * sizeof(TIO)) == 0;
     for (int64_t c0 = 0; c0 < n; c0 += kChunk) {
         const int64_t nc = n - c0 < kChunk ? n - c0 : kChunk;

@@ -229,13 +229,16 @@ void Server::loop()
                 slot_reqs_[slot].push_back(queued_[k]);
             }
             queued_.erase(queued_.begin(), queued_.begin() + k);
+            // the slot counts as busy before the lock is dropped, so drain() cannot
+            // observe an empty server while this batch is being launched
+            busy_slots_++;
             lk.unlock();
             const int rc = ex_->launch(slot, items);
             lk.lock();
             if (rc != SH_OK) {
+                busy_slots_--;
                 finish_locked(slot, rc);
             } else {
-                busy_slots_++;
                 st_.batches++;
             }
             prog = true;
@@ -330,13 +333,13 @@ int64_t Server::latencies(double* out, int64_t cap)
 
 namespace {
 
-// Runs nothing: a batch "finishes" after its output bytes at a fixed rate, and
-// every fail_every-th launch reports a failure.  Used to test scheduling without
+// Runs nothing: a launch takes launch_s of host time, a batch "finishes" after its
+// output bytes at a fixed rate, and every fail_every-th launch reports a failure.  Used to test scheduling without
 // a GPU; its arena has no memory (base address 0, offsets only).
 class SimExecutor final : public Executor {
 public:
-    SimExecutor(int n_slots, double bps, int fail_every)
-        : done_at_(n_slots), fail_(n_slots, false), bps_(bps), fail_every_(fail_every)
+    SimExecutor(int n_slots, double bps, int fail_every, double launch_s)
+        : done_at_(n_slots), fail_(n_slots, false), bps_(bps), fail_every_(fail_every), launch_s_(launch_s)
     {
     }
     int n_slots() const override { return int(done_at_.size()); }
@@ -345,6 +348,7 @@ public:
     void* arena_base() override { return nullptr; }
     int launch(int slot, const std::vector<Item>& items) override
     {
+        if (launch_s_ > 0) std::this_thread::sleep_for(std::chrono::duration<double>(launch_s_));
         double bytes = 0;
         for (const Item& it : items) bytes += double(out_bytes(it.atom, it.lmax));
         done_at_[slot] = Clock::now() + std::chrono::duration_cast<Clock::duration>(
@@ -364,15 +368,15 @@ private:
     std::vector<bool> fail_;
     double bps_;
     int fail_every_;
+    double launch_s_;  // host time one launch takes
     int64_t launches_ = 0;
 };
 
 }  // namespace
 
-std::unique_ptr<Executor> make_sim_executor(uint64_t budget, int n_slots, double bytes_per_s, int fail_every)
+std::unique_ptr<Executor> make_sim_executor(int n_slots, double bytes_per_s, int fail_every, double launch_s)
 {
-    (void)budget;
-    return std::unique_ptr<Executor>(new SimExecutor(n_slots, bytes_per_s, fail_every));
+    return std::unique_ptr<Executor>(new SimExecutor(n_slots, bytes_per_s, fail_every, launch_s));
 }
 
 }  // namespace shs

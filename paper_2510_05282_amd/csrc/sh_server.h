@@ -142,7 +142,7 @@ private:
     std::thread thr_;
 };
 
-std::unique_ptr<Executor> make_sim_executor(uint64_t budget, int n_slots, double bytes_per_s, int fail_every);
+std::unique_ptr<Executor> make_sim_executor(int n_slots, double bytes_per_s, int fail_every, double launch_s);
 std::unique_ptr<Executor> make_hip_executor(uint64_t budget, int n_slots, int* status);
 
 }  // namespace shs

@@ -18,13 +18,14 @@ class Server:
     executor that computes nothing (scheduling tests without a GPU)."""
 
     def __init__(self, budget_bytes: int, max_pending: int = 1 << 16, n_slots: int = 3,
-                 simulated: bool = False, sim_bytes_per_s: float = 5e12, sim_fail_every: int = 0):
+                 simulated: bool = False, sim_bytes_per_s: float = 5e12, sim_fail_every: int = 0,
+                 sim_launch_s: float = 0.0):
         h = ctypes.c_void_p()
         if simulated:
             check("sh_server_create_simulated",
                   lib().sh_server_create_simulated(int(budget_bytes), max_pending, n_slots,
                                                    float(sim_bytes_per_s), sim_fail_every,
-                                                   ctypes.byref(h)))
+                                                   float(sim_launch_s), ctypes.byref(h)))
         else:
             check("sh_server_create", lib().sh_server_create(int(budget_bytes), max_pending, n_slots,
                                                              ctypes.byref(h)))

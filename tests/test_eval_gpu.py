@@ -84,6 +84,18 @@ def test_ragged_sizes(dev, orc, n):
     assert np.abs(got.astype(LD) - orc.eval_xyz(9, pts)).max() <= TOL64
 
 
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 6, 7, 63, 65, 257, 1001, 4099])
+def test_ragged_sizes_fp32(dev, orc, n):
+    """FP32 runs four points per lane: remainders of 1-3 points take a second launch."""
+    pts = workloads.isotropic_points(n, 0.1, 5.0, seed=200 + n).astype(np.float32)
+    x = torch.from_numpy(pts).to(dev)
+    out = torch.full((100, n), float("nan"), dtype=torch.float32, device=dev)
+    sh.sh_eval_f32(9, x, out=out)
+    got = out.cpu().numpy()
+    assert np.isfinite(got).all()
+    assert np.abs(got.astype(LD) - orc.eval_xyz(9, pts)).max() <= TOL32
+
+
 def test_zero_points_is_noop(dev):
     x = torch.empty((0, 3), dtype=torch.float64, device=dev)
     y = sh.sh_eval(9, x)

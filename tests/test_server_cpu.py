@@ -131,3 +131,19 @@ def test_latency_includes_batch_time():
     lat = s.latencies_ms()
     assert lat[0] >= 80.0 * 0.99
     s.close()
+
+
+def test_drain_waits_for_batches_being_launched():
+    """Regression: drain() must not return while the scheduler is launching a batch
+    (a launch takes host time; the slot counts as busy from before it starts)."""
+    for _ in range(5):
+        s = _server(1 << 30, sim_launch_s=2e-3, sim_bytes_per_s=1e12)
+        a = s.add_atom(FAKE, [0, 0, 0], dtype=SH_F64, n=1000)
+        for k in range(60):
+            s.submit(a, k % 10, SH_REQ_AUTORELEASE)
+            if k % 7 == 0:
+                time.sleep(1e-3)
+        s.drain(30)
+        st = s.stats()
+        assert st["completed"] == 60, st
+        s.close()
