@@ -68,6 +68,28 @@ int sh_eval_f32(int lmax, int64_t n, const float *xyz, float *out, hipStream_t s
 int sh_eval_ld(int lmax, int64_t n, const void *xyz, void *out, int64_t ld, int dtype,
                hipStream_t stream);
 
+/* The paper's other two input interfaces (Section 2), same output layout:
+ *  - sh_eval_unit: xyz [n][3] already on the unit sphere (x^2 + y^2 + z^2 = 1,
+ *    eq. constraint); no normalisation is done, so other inputs give meaningless
+ *    values (the formulas hold only on the sphere).  The fastest interface.
+ *  - sh_eval_angles: polar angle theta[n] and azimuth phi[n] (radians); the unit
+ *    vector (sin t cos p, sin t sin p, cos t) is formed in FP64. */
+int sh_eval_unit(int lmax, int64_t n, const double *xyz, double *out, hipStream_t stream);
+int sh_eval_unit_f32(int lmax, int64_t n, const float *xyz, float *out, hipStream_t stream);
+int sh_eval_angles(int lmax, int64_t n, const double *theta, const double *phi, double *out,
+                   hipStream_t stream);
+int sh_eval_angles_f32(int lmax, int64_t n, const float *theta, const float *phi, float *out,
+                       hipStream_t stream);
+
+/* Complex harmonics Y_l^m (eq. sphericalfromlegendre, with the Condon-Shortley
+ * phase), built from the real ones (Section 3): Y_l^0 = R_l^0 and, for m > 0,
+ *   Y_l^m = (-1)^m (R_l^m + i R_l^-m) / sqrt(2),   Y_l^-m = (R_l^m - i R_l^-m) / sqrt(2)
+ * (so that Y_l^-m = (-1)^m conj(Y_l^m), eq. conjm).  out is [F][n] complex values
+ * stored as (re, im) pairs, i.e. 2 F n doubles (floats for the _f32 twin); row of
+ * (l, m) as elsewhere. */
+int sh_eval_complex(int lmax, int64_t n, const double *xyz, double *out, hipStream_t stream);
+int sh_eval_complex_f32(int lmax, int64_t n, const float *xyz, float *out, hipStream_t stream);
+
 /* Backward pass of sh_eval (vector-Jacobian product), for forces:
  *   grad_xyz[i][k] = sum_{row} grad_out[row][i] * d R_row(x_i) / d x_{i,k}
  * with xyz [n][3], grad_out [F][n] and grad_xyz [n][3], all double.  The
@@ -209,6 +231,18 @@ int sh_server_stats(sh_server_t srv, sh_server_stats_t *out);
 /* Copies up to cap completed-request latencies (ms, completion order) into
  * out_ms (may be NULL) and returns how many there are (negative on error). */
 int64_t sh_server_latencies(sh_server_t srv, double *out_ms, int64_t cap);
+
+/* Single-precision twin of sh_eval_grad: float xyz, grad_out and grad_xyz; the
+ * normalisation and 1/r in FP64, the polynomial gradients and the contraction
+ * over rows in FP32. */
+int sh_eval_grad_f32(int lmax, int64_t n, const float *xyz, const float *grad_out, float *grad_xyz,
+                     hipStream_t stream);
+
+/* Values and their Cartesian Jacobian in one pass, for forces:
+ *   out [F][n]      R_row(x_i)
+ *   jac [3][F][n]   d R_row(x_i) / d x_{i,k} at jac[(k * F + row) * n + i]
+ * (double).  Same derivative convention as sh_eval_grad; 0 at the origin. */
+int sh_eval_jac(int lmax, int64_t n, const double *xyz, double *out, double *jac, hipStream_t stream);
 
 /* Static text for a status code (never NULL). */
 const char *sh_strerror(int code);

@@ -55,6 +55,7 @@ def lib():
         L.orc_spline_eval.argtypes = [i32, ctypes.c_double, vp, vp, i64, vp, vp]
         L.orc_projectors.argtypes = [i32, i32, vp, vp, vp, vp, i32, ctypes.c_double, vp, vp, vp]
         L.orc_num_threads.restype = i32
+        L.orc_eval_complex_xyz.argtypes = [i32, i64, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -97,6 +98,16 @@ def eval_xyz(lmax: int, xyz) -> np.ndarray:
     out = np.empty((nfun(lmax), a.shape[0]), dtype=LD)
     _check(lib().orc_eval_xyz(lmax, a.shape[0], _p(a), _p(out)), "eval_xyz")
     return out
+
+
+def eval_complex_xyz(lmax: int, xyz):
+    """Complex harmonics Y_l^m at Cartesian points; returns (re, im), each [F][n]
+    long double."""
+    a = np.ascontiguousarray(np.asarray(xyz).reshape(-1, 3), dtype=np.float64)
+    re = np.empty((nfun(lmax), a.shape[0]), dtype=LD)
+    im = np.empty_like(re)
+    _check(lib().orc_eval_complex_xyz(lmax, a.shape[0], _p(a), _p(re), _p(im)), "eval_complex_xyz")
+    return re, im
 
 
 def eval_angles(lmax: int, theta, phi) -> np.ndarray:

@@ -20,8 +20,11 @@ SH_F64 = 0
 SH_F32 = 1
 
 __all__ = ["SH_LMAX", "Radial", "ShError", "SphericalHarmonics", "nfun", "row", "sh_eval",
-           "sh_eval_f32", "sh_eval_grad", "sh_eval_ld", "sh_projectors", "sh_projectors_f32",
-           "sh_radial_create", "sh_radial_destroy", "sh_strerror", "spherical_harmonics"]
+           "sh_eval_angles", "sh_eval_angles_f32", "sh_eval_complex", "sh_eval_complex_f32",
+           "sh_eval_f32", "sh_eval_grad", "sh_eval_grad_f32", "sh_eval_jac", "sh_eval_ld",
+           "sh_eval_unit", "sh_eval_unit_f32",
+           "sh_projectors", "sh_projectors_f32", "sh_radial_create", "sh_radial_destroy",
+           "sh_strerror", "spherical_harmonics"]
 
 
 def nfun(lmax: int) -> int:
@@ -99,45 +102,136 @@ def sh_eval_f32(lmax: int, xyz: torch.Tensor, out: torch.Tensor | None = None,
     return _eval("sh_eval_f32", torch.float32, lmax, xyz, out, stream)
 
 
+def sh_eval_unit(lmax: int, xyz: torch.Tensor, out: torch.Tensor | None = None, stream=None):
+    """Like sh_eval for points already on the unit sphere (no normalisation)."""
+    return _eval("sh_eval_unit", torch.float64, lmax, xyz, out, stream)
+
+
+def sh_eval_unit_f32(lmax: int, xyz: torch.Tensor, out: torch.Tensor | None = None, stream=None):
+    return _eval("sh_eval_unit_f32", torch.float32, lmax, xyz, out, stream)
+
+
+def _angles(fn, dtype, lmax, theta, phi, out, stream):
+    for name, t in (("theta", theta), ("phi", phi)):
+        if not t.is_cuda or t.dtype != dtype or t.dim() != 1 or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous 1-D {dtype} CUDA tensor")
+    n = theta.shape[0]
+    if phi.shape[0] != n:
+        raise ValueError("theta and phi must have the same length")
+    F = nfun(lmax)
+    if out is None:
+        out = torch.empty((F, n), dtype=dtype, device=theta.device)
+    elif out.dtype != dtype or tuple(out.shape) != (F, n) or not out.is_contiguous():
+        raise ValueError(f"out must be a contiguous [{F}, {n}] {dtype} tensor")
+    with torch.cuda.device(theta.device):
+        check(fn, getattr(lib(), fn)(lmax, n, theta.data_ptr(), phi.data_ptr(), out.data_ptr(),
+                                     _stream(theta.device, stream)))
+    return out
+
+
+def sh_eval_angles(lmax: int, theta: torch.Tensor, phi: torch.Tensor, out=None, stream=None):
+    """Real harmonics at polar angles theta[n] and azimuths phi[n] (float64)."""
+    return _angles("sh_eval_angles", torch.float64, lmax, theta, phi, out, stream)
+
+
+def sh_eval_angles_f32(lmax: int, theta: torch.Tensor, phi: torch.Tensor, out=None, stream=None):
+    return _angles("sh_eval_angles_f32", torch.float32, lmax, theta, phi, out, stream)
+
+
+def _complex(fn, dtype, ctype, lmax, xyz, out, stream):
+    n = _points(xyz, dtype)
+    F = nfun(lmax)
+    if out is None:
+        out = torch.empty((F, n), dtype=ctype, device=xyz.device)
+    elif out.dtype != ctype or tuple(out.shape) != (F, n) or not out.is_contiguous():
+        raise ValueError(f"out must be a contiguous [{F}, {n}] {ctype} tensor")
+    with torch.cuda.device(xyz.device):
+        check(fn, getattr(lib(), fn)(lmax, n, xyz.data_ptr(), out.data_ptr(), _stream(xyz.device, stream)))
+    return out
+
+
+def sh_eval_complex(lmax: int, xyz: torch.Tensor, out=None, stream=None) -> torch.Tensor:
+    """Complex harmonics Y_l^m [F, n] (complex128) of float64 points."""
+    return _complex("sh_eval_complex", torch.float64, torch.complex128, lmax, xyz, out, stream)
+
+
+def sh_eval_complex_f32(lmax: int, xyz: torch.Tensor, out=None, stream=None) -> torch.Tensor:
+    """Complex harmonics [F, n] (complex64) of float32 points."""
+    return _complex("sh_eval_complex_f32", torch.float32, torch.complex64, lmax, xyz, out, stream)
+
+
+def _grad(fn: str, dtype, lmax, xyz, grad_out, grad_xyz, stream):
+    n = _points(xyz, dtype)
+    F = nfun(lmax)
+    if (grad_out.dtype != dtype or grad_out.device != xyz.device
+            or tuple(grad_out.shape) != (F, n) or not grad_out.is_contiguous()):
+        raise ValueError(f"grad_out must be a contiguous [{F}, {n}] {dtype} tensor on {xyz.device}")
+    if grad_xyz is None:
+        grad_xyz = torch.empty((n, 3), dtype=dtype, device=xyz.device)
+    elif (grad_xyz.dtype != dtype or grad_xyz.device != xyz.device
+          or tuple(grad_xyz.shape) != (n, 3) or not grad_xyz.is_contiguous()):
+        raise ValueError(f"grad_xyz must be a contiguous [{n}, 3] {dtype} tensor on {xyz.device}")
+    with torch.cuda.device(xyz.device):
+        check(fn, getattr(lib(), fn)(lmax, n, xyz.data_ptr(), grad_out.data_ptr(), grad_xyz.data_ptr(),
+                                     _stream(xyz.device, stream)))
+    return grad_xyz
+
+
 def sh_eval_grad(lmax: int, xyz: torch.Tensor, grad_out: torch.Tensor,
                  grad_xyz: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     """Backward of sh_eval: grad_xyz[i, k] = sum_f grad_out[f, i] dR_f(x_i)/dx_{i,k}.
     xyz [n, 3] and grad_out [F, n] float64 -> [n, 3] float64."""
+    return _grad("sh_eval_grad", torch.float64, lmax, xyz, grad_out, grad_xyz, stream)
+
+
+def sh_eval_grad_f32(lmax: int, xyz: torch.Tensor, grad_out: torch.Tensor,
+                     grad_xyz: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Single-precision twin of sh_eval_grad (normalisation and 1/r in FP64)."""
+    return _grad("sh_eval_grad_f32", torch.float32, lmax, xyz, grad_out, grad_xyz, stream)
+
+
+def sh_eval_jac(lmax: int, xyz: torch.Tensor, out: torch.Tensor | None = None,
+                jac: torch.Tensor | None = None, stream=None):
+    """Values [F, n] and Jacobian [3, F, n] (jac[k, f, i] = dR_f(x_i)/dx_{i,k}) in one pass."""
     n = _points(xyz, torch.float64)
     F = nfun(lmax)
-    if (grad_out.dtype != torch.float64 or grad_out.device != xyz.device
-            or tuple(grad_out.shape) != (F, n) or not grad_out.is_contiguous()):
-        raise ValueError(f"grad_out must be a contiguous [{F}, {n}] float64 tensor on {xyz.device}")
-    if grad_xyz is None:
-        grad_xyz = torch.empty((n, 3), dtype=torch.float64, device=xyz.device)
-    elif (grad_xyz.dtype != torch.float64 or grad_xyz.device != xyz.device
-          or tuple(grad_xyz.shape) != (n, 3) or not grad_xyz.is_contiguous()):
-        raise ValueError(f"grad_xyz must be a contiguous [{n}, 3] float64 tensor on {xyz.device}")
+    if out is None:
+        out = torch.empty((F, n), dtype=torch.float64, device=xyz.device)
+    if jac is None:
+        jac = torch.empty((3, F, n), dtype=torch.float64, device=xyz.device)
+    for name, t, shape in (("out", out, (F, n)), ("jac", jac, (3, F, n))):
+        if (t.dtype != torch.float64 or t.device != xyz.device or tuple(t.shape) != shape
+                or not t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous {list(shape)} float64 tensor on {xyz.device}")
     with torch.cuda.device(xyz.device):
-        check("sh_eval_grad", lib().sh_eval_grad(lmax, n, xyz.data_ptr(), grad_out.data_ptr(),
-                                                 grad_xyz.data_ptr(), _stream(xyz.device, stream)))
-    return grad_xyz
+        check("sh_eval_jac", lib().sh_eval_jac(lmax, n, xyz.data_ptr(), out.data_ptr(), jac.data_ptr(),
+                                               _stream(xyz.device, stream)))
+    return out, jac
 
 
 class SphericalHarmonics(torch.autograd.Function):
-    """R_l^m(xyz) for l <= lmax as a differentiable op: forward is sh_eval, the
-    gradient with respect to the points is sh_eval_grad (float64)."""
+    """R_l^m(xyz) for l <= lmax as a differentiable op: forward is sh_eval
+    (sh_eval_f32 for float32 points), the gradient with respect to the points is
+    sh_eval_grad (sh_eval_grad_f32)."""
 
     @staticmethod
     def forward(ctx, xyz: torch.Tensor, lmax: int) -> torch.Tensor:
         xyz = xyz.contiguous()
         ctx.lmax = lmax
         ctx.save_for_backward(xyz)
-        return sh_eval(lmax, xyz)
+        return sh_eval(lmax, xyz) if xyz.dtype == torch.float64 else sh_eval_f32(lmax, xyz)
 
     @staticmethod
     def backward(ctx, grad_out: torch.Tensor):
         (xyz,) = ctx.saved_tensors
-        return sh_eval_grad(ctx.lmax, xyz, grad_out.contiguous()), None
+        g = grad_out.contiguous()
+        if xyz.dtype == torch.float64:
+            return sh_eval_grad(ctx.lmax, xyz, g), None
+        return sh_eval_grad_f32(ctx.lmax, xyz, g), None
 
 
 def spherical_harmonics(xyz: torch.Tensor, lmax: int) -> torch.Tensor:
-    """Differentiable real harmonics [F, n] of float64 points [n, 3]."""
+    """Differentiable real harmonics [F, n] of float64 or float32 points [n, 3]."""
     return SphericalHarmonics.apply(xyz, lmax)
 
 

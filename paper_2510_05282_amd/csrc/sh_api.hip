@@ -29,6 +29,33 @@ int hip_status(hipError_t e)
 bool bad_lmax(int lmax) { return lmax < 0 || lmax > SH_LMAX; }
 
 template <typename TIO>
+static int eval_unit(int lmax, int64_t n, const TIO *xyz, TIO *out, hipStream_t stream)
+{
+    if (bad_lmax(lmax) || n < 0) return SH_EINVAL;
+    if (n == 0) return SH_OK;
+    if (!xyz || !out) return SH_EINVAL;
+    return hip_status(shk::launch_fwd_unit<TIO>(lmax, n, xyz, out, n, stream));
+}
+
+template <typename TIO>
+static int eval_angles(int lmax, int64_t n, const TIO *theta, const TIO *phi, TIO *out, hipStream_t stream)
+{
+    if (bad_lmax(lmax) || n < 0) return SH_EINVAL;
+    if (n == 0) return SH_OK;
+    if (!theta || !phi || !out) return SH_EINVAL;
+    return hip_status(shk::launch_fwd_angles<TIO>(lmax, n, theta, phi, out, n, stream));
+}
+
+template <typename TIO>
+static int eval_complex(int lmax, int64_t n, const TIO *xyz, TIO *out, hipStream_t stream)
+{
+    if (bad_lmax(lmax) || n < 0) return SH_EINVAL;
+    if (n == 0) return SH_OK;
+    if (!xyz || !out) return SH_EINVAL;
+    return hip_status(shk::launch_fwd_complex<TIO>(lmax, n, xyz, out, n, stream));
+}
+
+template <typename TIO>
 static int projectors(int lmax, int n_atoms, const TIO *centers, const int64_t *offsets, int64_t n_points,
                       const TIO *points, sh_radial_t radial, const int32_t *table_of_atom, TIO *out,
                       hipStream_t stream)
@@ -73,6 +100,36 @@ int sh_eval_ld(int lmax, int64_t n, const void *xyz, void *out, int64_t ld, int 
                                              static_cast<float *>(out), ld, stream));
 }
 
+int sh_eval_unit(int lmax, int64_t n, const double *xyz, double *out, hipStream_t stream)
+{
+    return eval_unit<double>(lmax, n, xyz, out, stream);
+}
+
+int sh_eval_unit_f32(int lmax, int64_t n, const float *xyz, float *out, hipStream_t stream)
+{
+    return eval_unit<float>(lmax, n, xyz, out, stream);
+}
+
+int sh_eval_angles(int lmax, int64_t n, const double *theta, const double *phi, double *out, hipStream_t stream)
+{
+    return eval_angles<double>(lmax, n, theta, phi, out, stream);
+}
+
+int sh_eval_angles_f32(int lmax, int64_t n, const float *theta, const float *phi, float *out, hipStream_t stream)
+{
+    return eval_angles<float>(lmax, n, theta, phi, out, stream);
+}
+
+int sh_eval_complex(int lmax, int64_t n, const double *xyz, double *out, hipStream_t stream)
+{
+    return eval_complex<double>(lmax, n, xyz, out, stream);
+}
+
+int sh_eval_complex_f32(int lmax, int64_t n, const float *xyz, float *out, hipStream_t stream)
+{
+    return eval_complex<float>(lmax, n, xyz, out, stream);
+}
+
 int sh_eval(int lmax, int64_t n, const double *xyz, double *out, hipStream_t stream)
 {
     return sh_eval_ld(lmax, n, xyz, out, n, SH_F64, stream);
@@ -89,7 +146,24 @@ int sh_eval_grad(int lmax, int64_t n, const double *xyz, const double *grad_out,
     if (bad_lmax(lmax) || n < 0) return SH_EINVAL;
     if (n == 0) return SH_OK;
     if (!xyz || !grad_out || !grad_xyz) return SH_EINVAL;
-    return hip_status(shk::launch_grad(lmax, n, xyz, grad_out, n, grad_xyz, stream));
+    return hip_status(shk::launch_grad<double>(lmax, n, xyz, grad_out, n, grad_xyz, stream));
+}
+
+int sh_eval_grad_f32(int lmax, int64_t n, const float *xyz, const float *grad_out, float *grad_xyz,
+                     hipStream_t stream)
+{
+    if (bad_lmax(lmax) || n < 0) return SH_EINVAL;
+    if (n == 0) return SH_OK;
+    if (!xyz || !grad_out || !grad_xyz) return SH_EINVAL;
+    return hip_status(shk::launch_grad<float>(lmax, n, xyz, grad_out, n, grad_xyz, stream));
+}
+
+int sh_eval_jac(int lmax, int64_t n, const double *xyz, double *out, double *jac, hipStream_t stream)
+{
+    if (bad_lmax(lmax) || n < 0) return SH_EINVAL;
+    if (n == 0) return SH_OK;
+    if (!xyz || !out || !jac) return SH_EINVAL;
+    return hip_status(shk::launch_jac(lmax, n, xyz, out, jac, n, stream));
 }
 
 int sh_radial_create(int lmax, int n_tables, int n_r, double r_max, const double *host_values, sh_radial_t *out)

@@ -93,34 +93,34 @@ __host__ __device__ __forceinline__ Dual<T, N> operator+(scalar_t<T> c, const Du
 // Polynomial gradient contracted with an upstream gradient:
 //     v = sum_{l,m} g(row(l,m)) grad_u P_lm(u)   at the unit vector u = (x, y, z),
 // where g(row) returns the upstream value of a row.  Written to (vx, vy, vz).
-template <int LMAX, typename GetG>
-__host__ __device__ __forceinline__ void grad_unit(double x, double y, double z, GetG&& g,
-                                                   double& vx, double& vy, double& vz)
+// T is the arithmetic type of the polynomials (double or float).
+template <int LMAX, typename T, typename GetG>
+__host__ __device__ __forceinline__ void grad_unit(T x, T y, T z, GetG&& g, T& vx, T& vy, T& vz)
 {
-    using D1 = Dual<double, 1>;
-    using D2 = Dual<double, 2>;
+    using D1 = Dual<T, 1>;
+    using D2 = Dual<T, 2>;
     const D1 zd = D1::var(z, 0);
     const D2 xd = D2::var(x, 0), yd = D2::var(y, 1);
-    vx = 0.0;
-    vy = 0.0;
-    vz = 0.0;
+    vx = T(0);
+    vy = T(0);
+    vz = T(0);
     static_for<0, LMAX + 1>([&](auto mc) {
         constexpr int M = decltype(mc)::value;
         if constexpr (M == 0) {
             static_for<1, LMAX + 1>([&](auto lc) {
                 constexpr int L = decltype(lc)::value;
                 const D1 Z = zfac<D1, L, 0>(zd);
-                vz += g(row(L, 0)) * (K<double>::a(L, 0) * Z.d[0]);
+                vz += g(row(L, 0)) * (K<T>::a(L, 0) * Z.d[0]);
             });
         } else {
             const D2 S = shat<D2, M>(xd, yd);
             const D2 C = chat<D2, M>(xd, yd);
-            double aS = 0.0, aC = 0.0, bS = 0.0, bC = 0.0;
+            T aS = T(0), aC = T(0), bS = T(0), bC = T(0);
             static_for<M, LMAX + 1>([&](auto lc) {
                 constexpr int L = decltype(lc)::value;
                 const D1 Z = zfac<D1, L, M>(zd);
-                const double gs = g(row(L, -M)) * K<double>::a(L, M);
-                const double gc = g(row(L, M)) * K<double>::b(L, M);
+                const T gs = g(row(L, -M)) * K<T>::a(L, M);
+                const T gc = g(row(L, M)) * K<T>::b(L, M);
                 aS += gs * Z.v;
                 bS += gs * Z.d[0];
                 aC += gc * Z.v;
@@ -129,6 +129,41 @@ __host__ __device__ __forceinline__ void grad_unit(double x, double y, double z,
             vx += aS * S.d[0] + aC * C.d[0];
             vy += aS * S.d[1] + aC * C.d[1];
             vz += bS * S.v + bC * C.v;
+        }
+    });
+}
+
+// Every value and its polynomial gradient at the unit vector u = (x, y, z):
+// sink(row, P, dP/dx, dP/dy, dP/dz).  `keep` masks the rows that are nonzero at
+// u = 0 besides l = 0 (as in eval_unit).
+template <int LMAX, typename T, typename Sink>
+__host__ __device__ __forceinline__ void eval_unit_jac(T x, T y, T z, T keep, Sink&& sink)
+{
+    using D1 = Dual<T, 1>;
+    using D2 = Dual<T, 2>;
+    const D1 zd = D1::var(z, 0);
+    const D2 xd = D2::var(x, 0), yd = D2::var(y, 1);
+    static_for<0, LMAX + 1>([&](auto mc) {
+        constexpr int M = decltype(mc)::value;
+        if constexpr (M == 0) {
+            static_for<0, LMAX + 1>([&](auto lc) {
+                constexpr int L = decltype(lc)::value;
+                const D1 Z = zfac<D1, L, 0>(zd);
+                T v = K<T>::a(L, 0) * Z.v;
+                if constexpr (L > 0 && L % 2 == 0) v *= keep;
+                sink(row(L, 0), v, T(0), T(0), K<T>::a(L, 0) * Z.d[0]);
+            });
+        } else {
+            const D2 S = shat<D2, M>(xd, yd);
+            const D2 C = chat<D2, M>(xd, yd);
+            static_for<M, LMAX + 1>([&](auto lc) {
+                constexpr int L = decltype(lc)::value;
+                const D1 Z = zfac<D1, L, M>(zd);
+                const T a = K<T>::a(L, M) * Z.v, ad = K<T>::a(L, M) * Z.d[0];
+                const T b = K<T>::b(L, M) * Z.v, bd = K<T>::b(L, M) * Z.d[0];
+                sink(row(L, -M), a * S.v, a * S.d[0], a * S.d[1], ad * S.v);
+                sink(row(L, M), b * C.v, b * C.d[0], b * C.d[1], bd * C.v);
+            });
         }
     });
 }

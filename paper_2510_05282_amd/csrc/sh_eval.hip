@@ -29,56 +29,129 @@ constexpr int64_t kChunk = int64_t(1) << 28;
 // than a third of the CU's 160 KiB, so at most 2 workgroups are resident per CU.
 constexpr size_t kCapLds = 54 * 1024;
 
-template <int LMAX, typename TIO, int PPL>
-static hipError_t launch_one(const TIO* xyz, TIO* out, int64_t n, int64_t ld, hipStream_t s)
+// Input pointers of a launch that starts at point c0.
+template <In MODE, typename TIO>
+struct Inputs {
+    const TIO* a;
+    const TIO* b;
+    Inputs at(int64_t c0) const
+    {
+        if constexpr (MODE == In::kAngles) return {a + c0, b + c0};
+        else return {a + 3 * c0, b};
+    }
+};
+
+template <int LMAX, typename TIO, int PPL, In MODE>
+static hipError_t launch_one(Inputs<MODE, TIO> in, TIO* out, int64_t n, int64_t ld, hipStream_t s)
 {
     const int64_t nvec = n / PPL;
     const unsigned grid = unsigned((nvec + kFwdBlock - 1) / kFwdBlock);
-    hipLaunchKernelGGL((fwd_kernel<LMAX, TIO, PPL>), dim3(grid), dim3(kFwdBlock), PPL > 1 ? kCapLds : 0, s,
-                       xyz, out, uint32_t(n), ld);
+    hipLaunchKernelGGL((fwd_kernel<LMAX, TIO, PPL, MODE>), dim3(grid), dim3(kFwdBlock), PPL > 1 ? kCapLds : 0, s,
+                       in.a, out, uint32_t(n), ld, in.b);
     return hipGetLastError();
 }
 
-template <int LMAX, typename TIO>
-static hipError_t launch_fwd_l(int64_t n, const TIO* xyz, TIO* out, int64_t ld, hipStream_t s)
+template <int LMAX, typename TIO, In MODE>
+static hipError_t launch_fwd_l(int64_t n, Inputs<MODE, TIO> in, TIO* out, int64_t ld, hipStream_t s)
 {
     constexpr int kVec = 16 / sizeof(TIO);
-    const bool vec_ok = kVec > 1 && ld % kVec == 0 && reinterpret_cast<uintptr_t>(out) % (kVec * sizeof(TIO)) == 0;
+    const bool vec_ok = ld % kVec == 0 && reinterpret_cast<uintptr_t>(out) % (kVec * sizeof(TIO)) == 0;
     for (int64_t c0 = 0; c0 < n; c0 += kChunk) {
         const int64_t nc = n - c0 < kChunk ? n - c0 : kChunk;
         hipError_t e;
         if (vec_ok) {
             const int64_t nmain = nc - nc % kVec;
-            e = nmain ? launch_one<LMAX, TIO, kVec>(xyz + 3 * c0, out + c0, nmain, ld, s) : hipSuccess;
+            e = nmain ? launch_one<LMAX, TIO, kVec, MODE>(in.at(c0), out + c0, nmain, ld, s) : hipSuccess;
             if (e == hipSuccess && nmain < nc)
-                e = launch_one<LMAX, TIO, 1>(xyz + 3 * (c0 + nmain), out + c0 + nmain, nc - nmain, ld, s);
+                e = launch_one<LMAX, TIO, 1, MODE>(in.at(c0 + nmain), out + c0 + nmain, nc - nmain, ld, s);
         } else {
-            e = launch_one<LMAX, TIO, 1>(xyz + 3 * c0, out + c0, nc, ld, s);
+            e = launch_one<LMAX, TIO, 1, MODE>(in.at(c0), out + c0, nc, ld, s);
         }
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
+template <typename TIO, In MODE>
+static hipError_t dispatch(int lmax, int64_t n, Inputs<MODE, TIO> in, TIO* out, int64_t ld, hipStream_t s)
+{
+    switch (lmax) {
+    case 0: return launch_fwd_l<0, TIO, MODE>(n, in, out, ld, s);
+    case 1: return launch_fwd_l<1, TIO, MODE>(n, in, out, ld, s);
+    case 2: return launch_fwd_l<2, TIO, MODE>(n, in, out, ld, s);
+    case 3: return launch_fwd_l<3, TIO, MODE>(n, in, out, ld, s);
+    case 4: return launch_fwd_l<4, TIO, MODE>(n, in, out, ld, s);
+    case 5: return launch_fwd_l<5, TIO, MODE>(n, in, out, ld, s);
+    case 6: return launch_fwd_l<6, TIO, MODE>(n, in, out, ld, s);
+    case 7: return launch_fwd_l<7, TIO, MODE>(n, in, out, ld, s);
+    case 8: return launch_fwd_l<8, TIO, MODE>(n, in, out, ld, s);
+    case 9: return launch_fwd_l<9, TIO, MODE>(n, in, out, ld, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename TIO>
 hipError_t launch_fwd(int lmax, int64_t n, const TIO* xyz, TIO* out, int64_t ld, hipStream_t s)
 {
+    return dispatch<TIO, In::kXyz>(lmax, n, {xyz, nullptr}, out, ld, s);
+}
+
+template <typename TIO>
+hipError_t launch_fwd_unit(int lmax, int64_t n, const TIO* xyz, TIO* out, int64_t ld, hipStream_t s)
+{
+    return dispatch<TIO, In::kUnit>(lmax, n, {xyz, nullptr}, out, ld, s);
+}
+
+template <typename TIO>
+hipError_t launch_fwd_angles(int lmax, int64_t n, const TIO* theta, const TIO* phi, TIO* out, int64_t ld,
+                             hipStream_t s)
+{
+    return dispatch<TIO, In::kAngles>(lmax, n, {theta, phi}, out, ld, s);
+}
+
+template <int LMAX, typename TIO>
+static hipError_t launch_complex_l(int64_t n, const TIO* xyz, TIO* out, int64_t ld, hipStream_t s)
+{
+    // one complex (two TIO) per lane and row: 16-byte stores in FP64, capped like the 16-byte real kernels
+    const size_t lds = sizeof(TIO) == 8 ? kCapLds : 0;
+    for (int64_t c0 = 0; c0 < n; c0 += kChunk) {
+        const int64_t nc = n - c0 < kChunk ? n - c0 : kChunk;
+        const unsigned grid = unsigned((nc + kFwdBlock - 1) / kFwdBlock);
+        hipLaunchKernelGGL((fwd_complex_kernel<LMAX, TIO>), dim3(grid), dim3(kFwdBlock), lds, s, xyz + 3 * c0,
+                           out + 2 * c0, uint32_t(nc), ld);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <typename TIO>
+hipError_t launch_fwd_complex(int lmax, int64_t n, const TIO* xyz, TIO* out, int64_t ld, hipStream_t s)
+{
     switch (lmax) {
-    case 0: return launch_fwd_l<0, TIO>(n, xyz, out, ld, s);
-    case 1: return launch_fwd_l<1, TIO>(n, xyz, out, ld, s);
-    case 2: return launch_fwd_l<2, TIO>(n, xyz, out, ld, s);
-    case 3: return launch_fwd_l<3, TIO>(n, xyz, out, ld, s);
-    case 4: return launch_fwd_l<4, TIO>(n, xyz, out, ld, s);
-    case 5: return launch_fwd_l<5, TIO>(n, xyz, out, ld, s);
-    case 6: return launch_fwd_l<6, TIO>(n, xyz, out, ld, s);
-    case 7: return launch_fwd_l<7, TIO>(n, xyz, out, ld, s);
-    case 8: return launch_fwd_l<8, TIO>(n, xyz, out, ld, s);
-    case 9: return launch_fwd_l<9, TIO>(n, xyz, out, ld, s);
+    case 0: return launch_complex_l<0, TIO>(n, xyz, out, ld, s);
+    case 1: return launch_complex_l<1, TIO>(n, xyz, out, ld, s);
+    case 2: return launch_complex_l<2, TIO>(n, xyz, out, ld, s);
+    case 3: return launch_complex_l<3, TIO>(n, xyz, out, ld, s);
+    case 4: return launch_complex_l<4, TIO>(n, xyz, out, ld, s);
+    case 5: return launch_complex_l<5, TIO>(n, xyz, out, ld, s);
+    case 6: return launch_complex_l<6, TIO>(n, xyz, out, ld, s);
+    case 7: return launch_complex_l<7, TIO>(n, xyz, out, ld, s);
+    case 8: return launch_complex_l<8, TIO>(n, xyz, out, ld, s);
+    case 9: return launch_complex_l<9, TIO>(n, xyz, out, ld, s);
     default: return hipErrorInvalidValue;
     }
 }
 
 template hipError_t launch_fwd<double>(int, int64_t, const double*, double*, int64_t, hipStream_t);
 template hipError_t launch_fwd<float>(int, int64_t, const float*, float*, int64_t, hipStream_t);
+template hipError_t launch_fwd_unit<double>(int, int64_t, const double*, double*, int64_t, hipStream_t);
+template hipError_t launch_fwd_unit<float>(int, int64_t, const float*, float*, int64_t, hipStream_t);
+template hipError_t launch_fwd_angles<double>(int, int64_t, const double*, const double*, double*, int64_t,
+                                              hipStream_t);
+template hipError_t launch_fwd_angles<float>(int, int64_t, const float*, const float*, float*, int64_t,
+                                             hipStream_t);
+template hipError_t launch_fwd_complex<double>(int, int64_t, const double*, double*, int64_t, hipStream_t);
+template hipError_t launch_fwd_complex<float>(int, int64_t, const float*, float*, int64_t, hipStream_t);
 
 }  // namespace shk

@@ -40,13 +40,43 @@ __device__ __forceinline__ auto& lane(V& v, int k)
     else return reinterpret_cast<scalar_t<V>*>(&v)[k];
 }
 
-// out is [F][ld], xyz is [n][3]; n * sizeof(TIO) < 2^31 so per-row byte offsets
+// The paper's three input interfaces (Section 2): Cartesian points (normalised
+// here), points already on the unit sphere, and the angles (theta, phi).
+enum class In { kXyz, kUnit, kAngles };
+
+// Unit vector (in FP64) and origin mask of point i of the input.
+template <In MODE, typename TIO>
+__device__ __forceinline__ void load_unit(const TIO* __restrict__ a, const TIO* __restrict__ b, uint32_t i,
+                                          double& xb, double& yb, double& zb, double& kb)
+{
+    if constexpr (MODE == In::kXyz) {
+        const TIO* p = a + 3 * size_t(i);
+        normalize(double(p[0]), double(p[1]), double(p[2]), xb, yb, zb, kb);
+    } else if constexpr (MODE == In::kUnit) {
+        const TIO* p = a + 3 * size_t(i);
+        xb = double(p[0]);
+        yb = double(p[1]);
+        zb = double(p[2]);
+        kb = 1.0;
+    } else {
+        double st, ct, sp, cp;
+        sincos(double(a[i]), &st, &ct);
+        sincos(double(b[i]), &sp, &cp);
+        xb = st * cp;
+        yb = st * sp;
+        zb = ct;
+        kb = 1.0;
+    }
+}
+
+// out is [F][ld]; the input is xyz [n][3] (kXyz, kUnit) or theta = xyz[n],
+// phi = in1[n] (kAngles); n * sizeof(TIO) < 2^31 so per-row byte offsets
 // fit 32 bits (the host splits larger batches).  With PPL > 1 the host
 // guarantees n % PPL == 0, ld % PPL == 0 and a PPL * sizeof(TIO)-aligned out
 // (a remainder of fewer than PPL points goes to a PPL = 1 launch).
-template <int LMAX, typename TIO, int PPL>
+template <int LMAX, typename TIO, int PPL, In MODE = In::kXyz>
 __global__ __launch_bounds__(kFwdBlock) void fwd_kernel(const TIO* __restrict__ xyz, TIO* __restrict__ out,
-                                                        uint32_t n, int64_t ld)
+                                                        uint32_t n, int64_t ld, const TIO* __restrict__ in1)
 {
     using V = typename vec_of<TIO, PPL>::type;
     const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
@@ -56,9 +86,8 @@ __global__ __launch_bounds__(kFwdBlock) void fwd_kernel(const TIO* __restrict__ 
     V x, y, z, k;
 #pragma unroll
     for (int q = 0; q < PPL; ++q) {
-        const TIO* p = xyz + 3 * size_t(i0 + q);
         double xb, yb, zb, kb;
-        normalize(double(p[0]), double(p[1]), double(p[2]), xb, yb, zb, kb);
+        load_unit<MODE, TIO>(xyz, in1, i0 + q, xb, yb, zb, kb);
         lane<V, PPL>(x, q) = TIO(xb);
         lane<V, PPL>(y, q) = TIO(yb);
         lane<V, PPL>(z, q) = TIO(zb);
@@ -67,6 +96,46 @@ __global__ __launch_bounds__(kFwdBlock) void fwd_kernel(const TIO* __restrict__ 
     const uint32_t boff = i0 * uint32_t(sizeof(TIO));
     eval_unit<LMAX, V>(x, y, z, k, [&](int r, V v) {
         *reinterpret_cast<V*>(reinterpret_cast<char*>(out + int64_t(r) * ld) + boff) = v;
+    });
+}
+
+// Complex harmonics from the real ones (Section 3): for m > 0
+//     Y_l^m  = (-1)^m (R_l^m + i R_l^-m) / sqrt(2),   Y_l^-m = (R_l^m - i R_l^-m) / sqrt(2),
+// and Y_l^0 = R_l^0.  (eq. real_harmomics inverted; the paper's printed relation
+// omits the 1/sqrt(2).)  Output: out[row][i] as (re, im) pairs, [F][ld] complex.
+// Each lane stores one complex value (two TIO) per row.
+template <int LMAX, typename TIO>
+__global__ __launch_bounds__(kFwdBlock) void fwd_complex_kernel(const TIO* __restrict__ xyz,
+                                                                TIO* __restrict__ out, uint32_t n, int64_t ld)
+{
+    using C = typename vec_of<TIO, 2>::type;
+    const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t i = b * kFwdBlock + threadIdx.x;
+    if (i >= n) return;
+    double xb, yb, zb, kb;
+    load_unit<In::kXyz, TIO>(xyz, nullptr, i, xb, yb, zb, kb);
+    const uint32_t boff = i * uint32_t(sizeof(C));
+    auto store = [&](int r, TIO re, TIO im) {
+        C v;
+        v.x = re;
+        v.y = im;
+        *reinterpret_cast<C*>(reinterpret_cast<char*>(reinterpret_cast<C*>(out) + int64_t(r) * ld) + boff) = v;
+    };
+    const TIO h = TIO(0.70710678118654752440);  // 1/sqrt(2)
+    TIO sin_part = TIO(0);
+    eval_unit<LMAX, TIO>(TIO(xb), TIO(yb), TIO(zb), TIO(kb), [&](int r, TIO v) {
+        int l = 0;
+        while ((l + 1) * (l + 1) <= r) ++l;
+        const int m = r - l * l - l;
+        if (m == 0) {
+            store(r, v, TIO(0));
+        } else if (m < 0) {
+            sin_part = v;  // R_l^-|m| arrives just before R_l^|m|
+        } else {
+            const TIO re = h * v, im = h * sin_part;
+            store(r, (m & 1) ? -re : re, (m & 1) ? -im : im);
+            store(l * l + l - m, re, -im);
+        }
     });
 }
 

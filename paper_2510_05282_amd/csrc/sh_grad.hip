@@ -10,7 +10,8 @@
 // (grad_unit in sh_dual.h).
 // One thread per point; G is read row by row (coalesced across the wave), the
 // three gradient components are written per point.  Memory traffic per point:
-// 24 B in (xyz) + 8F B (G) + 24 B out; this path is bound by reading G.
+// 3s B in (xyz) + F s B (G) + 3s B out (s = element size); this path is bound by
+// reading G.  The same file holds the fused value + Jacobian kernel.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -23,40 +24,40 @@ namespace shk {
 constexpr int kGradBlock = 256;
 constexpr int64_t kGradChunk = int64_t(1) << 28;
 
-template <int LMAX>
-__global__ __launch_bounds__(kGradBlock) void grad_kernel(const double* __restrict__ xyz,
-                                                          const double* __restrict__ G,
-                                                          double* __restrict__ gxyz, uint32_t n,
-                                                          int64_t ldg)
+// TIO is the element type of xyz, G and the result; the normalisation and 1/r
+// run in FP64, the polynomials and the contraction in TIO.
+template <int LMAX, typename TIO>
+__global__ __launch_bounds__(kGradBlock) void grad_kernel(const TIO* __restrict__ xyz, const TIO* __restrict__ G,
+                                                          TIO* __restrict__ gxyz, uint32_t n, int64_t ldg)
 {
     const uint32_t i = blockIdx.x * kGradBlock + threadIdx.x;
     if (i >= n) return;
-    const double* p = xyz + 3 * size_t(i);
+    const TIO* p = xyz + 3 * size_t(i);
     double xb, yb, zb, keep, rinv;
-    normalize(p[0], p[1], p[2], xb, yb, zb, keep, rinv);
-    const uint32_t boff = i * uint32_t(sizeof(double));
+    normalize(double(p[0]), double(p[1]), double(p[2]), xb, yb, zb, keep, rinv);
+    const uint32_t boff = i * uint32_t(sizeof(TIO));
     auto g_at = [&](int r) {
         return __builtin_nontemporal_load(
-            reinterpret_cast<const double*>(reinterpret_cast<const char*>(G + int64_t(r) * ldg) + boff));
+            reinterpret_cast<const TIO*>(reinterpret_cast<const char*>(G + int64_t(r) * ldg) + boff));
     };
     (void)keep;  // the origin needs no mask here: rinv = 0 there, so the gradient is 0
-    double vx, vy, vz;
-    grad_unit<LMAX>(xb, yb, zb, g_at, vx, vy, vz);
-    const double uv = xb * vx + yb * vy + zb * vz;
-    double* o = gxyz + 3 * size_t(i);
-    o[0] = rinv * (vx - xb * uv);
-    o[1] = rinv * (vy - yb * uv);
-    o[2] = rinv * (vz - zb * uv);
+    TIO vx, vy, vz;
+    const TIO x = TIO(xb), y = TIO(yb), z = TIO(zb);
+    grad_unit<LMAX, TIO>(x, y, z, g_at, vx, vy, vz);
+    const double uv = xb * double(vx) + yb * double(vy) + zb * double(vz);
+    TIO* o = gxyz + 3 * size_t(i);
+    o[0] = TIO(rinv * (double(vx) - xb * uv));
+    o[1] = TIO(rinv * (double(vy) - yb * uv));
+    o[2] = TIO(rinv * (double(vz) - zb * uv));
 }
 
-template <int LMAX>
-static hipError_t launch_grad_l(int64_t n, const double* xyz, const double* G, int64_t ldg, double* gxyz,
-                                hipStream_t s)
+template <int LMAX, typename TIO>
+static hipError_t launch_grad_l(int64_t n, const TIO* xyz, const TIO* G, int64_t ldg, TIO* gxyz, hipStream_t s)
 {
     for (int64_t c0 = 0; c0 < n; c0 += kGradChunk) {
         const int64_t nc = n - c0 < kGradChunk ? n - c0 : kGradChunk;
         const unsigned grid = unsigned((nc + kGradBlock - 1) / kGradBlock);
-        hipLaunchKernelGGL((grad_kernel<LMAX>), dim3(grid), dim3(kGradBlock), 0, s, xyz + 3 * c0, G + c0,
+        hipLaunchKernelGGL((grad_kernel<LMAX, TIO>), dim3(grid), dim3(kGradBlock), 0, s, xyz + 3 * c0, G + c0,
                            gxyz + 3 * c0, uint32_t(nc), ldg);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -64,20 +65,83 @@ static hipError_t launch_grad_l(int64_t n, const double* xyz, const double* G, i
     return hipSuccess;
 }
 
-hipError_t launch_grad(int lmax, int64_t n, const double* xyz, const double* G, int64_t ldg, double* gxyz,
-                       hipStream_t s)
+template <typename TIO>
+hipError_t launch_grad(int lmax, int64_t n, const TIO* xyz, const TIO* G, int64_t ldg, TIO* gxyz, hipStream_t s)
 {
     switch (lmax) {
-    case 0: return launch_grad_l<0>(n, xyz, G, ldg, gxyz, s);
-    case 1: return launch_grad_l<1>(n, xyz, G, ldg, gxyz, s);
-    case 2: return launch_grad_l<2>(n, xyz, G, ldg, gxyz, s);
-    case 3: return launch_grad_l<3>(n, xyz, G, ldg, gxyz, s);
-    case 4: return launch_grad_l<4>(n, xyz, G, ldg, gxyz, s);
-    case 5: return launch_grad_l<5>(n, xyz, G, ldg, gxyz, s);
-    case 6: return launch_grad_l<6>(n, xyz, G, ldg, gxyz, s);
-    case 7: return launch_grad_l<7>(n, xyz, G, ldg, gxyz, s);
-    case 8: return launch_grad_l<8>(n, xyz, G, ldg, gxyz, s);
-    case 9: return launch_grad_l<9>(n, xyz, G, ldg, gxyz, s);
+    case 0: return launch_grad_l<0, TIO>(n, xyz, G, ldg, gxyz, s);
+    case 1: return launch_grad_l<1, TIO>(n, xyz, G, ldg, gxyz, s);
+    case 2: return launch_grad_l<2, TIO>(n, xyz, G, ldg, gxyz, s);
+    case 3: return launch_grad_l<3, TIO>(n, xyz, G, ldg, gxyz, s);
+    case 4: return launch_grad_l<4, TIO>(n, xyz, G, ldg, gxyz, s);
+    case 5: return launch_grad_l<5, TIO>(n, xyz, G, ldg, gxyz, s);
+    case 6: return launch_grad_l<6, TIO>(n, xyz, G, ldg, gxyz, s);
+    case 7: return launch_grad_l<7, TIO>(n, xyz, G, ldg, gxyz, s);
+    case 8: return launch_grad_l<8, TIO>(n, xyz, G, ldg, gxyz, s);
+    case 9: return launch_grad_l<9, TIO>(n, xyz, G, ldg, gxyz, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template hipError_t launch_grad<double>(int, int64_t, const double*, const double*, int64_t, double*,
+                                        hipStream_t);
+template hipError_t launch_grad<float>(int, int64_t, const float*, const float*, int64_t, float*, hipStream_t);
+
+// ---------------------------------------------------------------- fused value + Jacobian
+
+// Values out[F][ld] and the Jacobian jac[3][F][ld] (d R_f / d x_k at
+// jac[(k F + f) ld + i]) in one pass: the dual-number core gives P and grad_u P,
+// which is projected with (1/r)(I - u u^T).
+template <int LMAX>
+__global__ __launch_bounds__(kGradBlock) void jac_kernel(const double* __restrict__ xyz, double* __restrict__ out,
+                                                         double* __restrict__ jac, uint32_t n, int64_t ld)
+{
+    constexpr int F = nfun(LMAX);
+    const uint32_t i = blockIdx.x * kGradBlock + threadIdx.x;
+    if (i >= n) return;
+    const double* p = xyz + 3 * size_t(i);
+    double xb, yb, zb, keep, rinv;
+    normalize(p[0], p[1], p[2], xb, yb, zb, keep, rinv);
+    const uint32_t boff = i * uint32_t(sizeof(double));
+    auto at = [&](double* base, int64_t r) {
+        return reinterpret_cast<double*>(reinterpret_cast<char*>(base + r * ld) + boff);
+    };
+    eval_unit_jac<LMAX, double>(xb, yb, zb, keep, [&](int f, double v, double gx, double gy, double gz) {
+        const double ug = xb * gx + yb * gy + zb * gz;
+        *at(out, f) = v;
+        *at(jac, f) = rinv * (gx - xb * ug);
+        *at(jac, F + f) = rinv * (gy - yb * ug);
+        *at(jac, 2 * F + f) = rinv * (gz - zb * ug);
+    });
+}
+
+template <int LMAX>
+static hipError_t launch_jac_l(int64_t n, const double* xyz, double* out, double* jac, int64_t ld, hipStream_t s)
+{
+    for (int64_t c0 = 0; c0 < n; c0 += kGradChunk) {
+        const int64_t nc = n - c0 < kGradChunk ? n - c0 : kGradChunk;
+        const unsigned grid = unsigned((nc + kGradBlock - 1) / kGradBlock);
+        hipLaunchKernelGGL((jac_kernel<LMAX>), dim3(grid), dim3(kGradBlock), 0, s, xyz + 3 * c0, out + c0,
+                           jac + c0, uint32_t(nc), ld);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_jac(int lmax, int64_t n, const double* xyz, double* out, double* jac, int64_t ld, hipStream_t s)
+{
+    switch (lmax) {
+    case 0: return launch_jac_l<0>(n, xyz, out, jac, ld, s);
+    case 1: return launch_jac_l<1>(n, xyz, out, jac, ld, s);
+    case 2: return launch_jac_l<2>(n, xyz, out, jac, ld, s);
+    case 3: return launch_jac_l<3>(n, xyz, out, jac, ld, s);
+    case 4: return launch_jac_l<4>(n, xyz, out, jac, ld, s);
+    case 5: return launch_jac_l<5>(n, xyz, out, jac, ld, s);
+    case 6: return launch_jac_l<6>(n, xyz, out, jac, ld, s);
+    case 7: return launch_jac_l<7>(n, xyz, out, jac, ld, s);
+    case 8: return launch_jac_l<8>(n, xyz, out, jac, ld, s);
+    case 9: return launch_jac_l<9>(n, xyz, out, jac, ld, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -19,10 +19,22 @@ namespace shk {
 // Forward values R_l^m for l <= lmax at n points xyz[n][3] into out[F][ld].
 template <typename TIO>
 hipError_t launch_fwd(int lmax, int64_t n, const TIO* xyz, TIO* out, int64_t ld, hipStream_t s);
+// The same from unit vectors (no normalisation) and from angles theta[n], phi[n].
+template <typename TIO>
+hipError_t launch_fwd_unit(int lmax, int64_t n, const TIO* xyz, TIO* out, int64_t ld, hipStream_t s);
+template <typename TIO>
+hipError_t launch_fwd_angles(int lmax, int64_t n, const TIO* theta, const TIO* phi, TIO* out, int64_t ld,
+                             hipStream_t s);
+// Complex harmonics Y_l^m into out[F][ld] of (re, im) pairs (ld in complex elements).
+template <typename TIO>
+hipError_t launch_fwd_complex(int lmax, int64_t n, const TIO* xyz, TIO* out, int64_t ld, hipStream_t s);
 
 // Vector-Jacobian product: gxyz[n][3] = sum_f G[f][i] dR_f/dx at xyz[n][3]; G is [F][ldg].
-hipError_t launch_grad(int lmax, int64_t n, const double* xyz, const double* G, int64_t ldg, double* gxyz,
-                       hipStream_t s);
+template <typename TIO>
+hipError_t launch_grad(int lmax, int64_t n, const TIO* xyz, const TIO* G, int64_t ldg, TIO* gxyz, hipStream_t s);
+
+// Values out[F][ld] and Jacobian jac[3][F][ld] in one pass (FP64).
+hipError_t launch_jac(int lmax, int64_t n, const double* xyz, double* out, double* jac, int64_t ld, hipStream_t s);
 
 // Arguments of the flat projector kernel (device pointers unless noted).
 template <typename TIO>

@@ -34,3 +34,32 @@ static void grad(long n, const double *u, const double *G, double *out)
 
 extern "C" void core_grad9(long n, const double *u, const double *G, double *out) { grad<9>(n, u, G, out); }
 extern "C" void core_grad6(long n, const double *u, const double *G, double *out) { grad<6>(n, u, G, out); }
+
+// FP32 gradient core at float unit vectors.
+extern "C" void core_grad9_f32(long n, const float *u, const float *G, float *out)
+{
+    for (long i = 0; i < n; ++i) {
+        float vx, vy, vz;
+        shk::grad_unit<9>(u[3 * i], u[3 * i + 1], u[3 * i + 2], [&](int r) { return G[r * n + i]; }, vx, vy, vz);
+        const float uv = u[3 * i] * vx + u[3 * i + 1] * vy + u[3 * i + 2] * vz;
+        out[3 * i] = vx - u[3 * i] * uv;
+        out[3 * i + 1] = vy - u[3 * i + 1] * uv;
+        out[3 * i + 2] = vz - u[3 * i + 2] * uv;
+    }
+}
+
+// Values and projected Jacobian at unit vectors (r = 1): val[F][n], jac[3][F][n].
+extern "C" void core_jac9(long n, const double *u, double *val, double *jac)
+{
+    const int F = 100;
+    for (long i = 0; i < n; ++i) {
+        const double x = u[3 * i], y = u[3 * i + 1], z = u[3 * i + 2];
+        shk::eval_unit_jac<9, double>(x, y, z, 1.0, [&](int f, double v, double gx, double gy, double gz) {
+            const double ug = x * gx + y * gy + z * gz;
+            val[f * n + i] = v;
+            jac[(0 * F + f) * n + i] = gx - x * ug;
+            jac[(1 * F + f) * n + i] = gy - y * ug;
+            jac[(2 * F + f) * n + i] = gz - z * ug;
+        });
+    }
+}

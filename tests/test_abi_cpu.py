@@ -80,3 +80,26 @@ def test_radial_and_projector_validation(L):
     assert L.sh_projectors(3, 1, fake, fake, 10, fake, None, None, fake, None) == 1  # no radial
     assert L.sh_projectors(-1, 1, fake, fake, 10, fake, fake, None, fake, None) == 1
     assert L.sh_projectors_f32(3, -1, fake, fake, 10, fake, fake, None, fake, None) == 1
+
+
+def test_grad_f32_and_jac_validation(L):
+    fake = ctypes.c_void_p(0x1000)
+    assert L.sh_eval_grad_f32(10, 5, fake, fake, fake, None) == 1
+    assert L.sh_eval_grad_f32(3, 5, None, fake, fake, None) == 1
+    assert L.sh_eval_grad_f32(3, 0, None, None, None, None) == 0
+    assert L.sh_eval_jac(-1, 5, fake, fake, fake, None) == 1
+    assert L.sh_eval_jac(3, 5, fake, None, fake, None) == 1
+    assert L.sh_eval_jac(3, 5, fake, fake, None, None) == 1
+    assert L.sh_eval_jac(9, 0, None, None, None, None) == 0
+
+
+def test_interface_variants_validation(L):
+    fake = ctypes.c_void_p(0x1000)
+    for fn in ("sh_eval_unit", "sh_eval_unit_f32", "sh_eval_complex", "sh_eval_complex_f32"):
+        assert getattr(L, fn)(10, 5, fake, fake, None) == 1
+        assert getattr(L, fn)(3, 5, None, fake, None) == 1
+        assert getattr(L, fn)(3, 0, None, None, None) == 0
+    for fn in ("sh_eval_angles", "sh_eval_angles_f32"):
+        assert getattr(L, fn)(10, 5, fake, fake, fake, None) == 1
+        assert getattr(L, fn)(3, 5, fake, None, fake, None) == 1
+        assert getattr(L, fn)(3, 0, None, None, None, None) == 0

@@ -90,3 +90,27 @@ def test_core_gradient_matches_oracle(core, orc, lmax, fn):
     scale = 1 + np.abs(ref).max(axis=1, keepdims=True)
     err = (np.abs(out.astype(LD) - ref) / scale).max()
     assert err <= 1e-12, err
+
+
+def test_core_gradient_fp32(core, orc):
+    core.core_grad9_f32.argtypes = [ctypes.c_long, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    u = _units(_pts(), np.float32)
+    G = np.random.default_rng(42).standard_normal((100, u.shape[0])).astype(np.float32)
+    out = np.empty((u.shape[0], 3), dtype=np.float32)
+    core.core_grad9_f32(u.shape[0], u.ctypes.data, G.ctypes.data, out.ctypes.data)
+    ref = orc.grad_xyz(9, u.astype(np.float64), G.astype(np.float64))
+    scale = 1 + np.abs(ref).max(axis=1, keepdims=True)
+    err = (np.abs(out.astype(LD) - ref) / scale).max()
+    assert err <= 2e-5, err
+
+
+def test_core_values_and_jacobian(core, orc):
+    core.core_jac9.argtypes = [ctypes.c_long, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    u = _units(_pts()[:5000], np.float64)
+    n = u.shape[0]
+    val = np.empty((100, n))
+    jac = np.empty((3, 100, n))
+    core.core_jac9(n, u.ctypes.data, val.ctypes.data, jac.ctypes.data)
+    assert np.abs(val.astype(LD) - orc.eval_xyz(9, u)).max() <= 3e-14
+    J = orc.jacobian_xyz(9, u)
+    assert np.abs(jac.astype(LD) - J).max() <= 1e-12 * (1 + float(np.abs(J).max()))

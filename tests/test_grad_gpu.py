@@ -126,3 +126,42 @@ def test_autograd_function(dev):
     small = torch.from_numpy(pts[:6]).to(dev).requires_grad_(True)
     assert torch.autograd.gradcheck(lambda t: sh.spherical_harmonics(t, 4), (small,), eps=1e-6,
                                     atol=1e-7, rtol=1e-6)
+
+
+def test_grad_fp32_parity(dev, orc):
+    """FP32 backward against the oracle at the float inputs (upstream gradient in
+    float, widened): |dg|_inf <= 2e-5 (1 + |g|_inf)."""
+    for lmax in (1, 6, 9):
+        pts = workloads.points_gradient(n=20000, seed=30 + lmax).astype(np.float32)
+        F = (lmax + 1) ** 2
+        G = np.random.default_rng(lmax).standard_normal((F, pts.shape[0])).astype(np.float32)
+        g = sh.sh_eval_grad_f32(lmax, torch.from_numpy(pts).to(dev), torch.from_numpy(G).to(dev))
+        ref = orc.grad_xyz(lmax, pts.astype(np.float64), G.astype(np.float64))
+        err = _rel_err(g.cpu().numpy(), ref)
+        _say("  fp32 grad lmax", lmax, "max relative err:", float(err))
+        assert err <= 2e-5
+
+
+def test_fused_values_and_jacobian(dev, orc):
+    pts = np.concatenate([workloads.points_gradient(n=5000, seed=40),
+                          np.array([[0, 0, 1.5], [0, 0, 0.0], [2.0, 0, 0]])])
+    for lmax in (0, 3, 9):
+        F = (lmax + 1) ** 2
+        y, j = sh.sh_eval_jac(lmax, torch.from_numpy(pts).to(dev))
+        y, j = y.cpu().numpy(), j.cpu().numpy()
+        assert np.abs(y.astype(LD) - orc.eval_xyz(lmax, pts)).max() <= 1e-13
+        J = orc.jacobian_xyz(lmax, pts)
+        scale = 1 + np.abs(J.astype(np.float64)).max()
+        assert np.abs(j.astype(LD) - J).max() <= 1e-12 * scale
+        assert np.all(j[:, :, -2] == 0)  # origin
+        assert y.shape == (F, pts.shape[0])
+
+
+def test_autograd_fp32(dev):
+    pts = workloads.points_gradient(n=3000, seed=12).astype(np.float32)
+    x = torch.from_numpy(pts).to(dev).requires_grad_(True)
+    y = sh.spherical_harmonics(x, 4)
+    assert y.dtype == torch.float32
+    G = torch.from_numpy(np.random.default_rng(13).standard_normal((25, 3000)).astype(np.float32)).to(dev)
+    (y * G).sum().backward()
+    assert torch.equal(x.grad, sh.sh_eval_grad_f32(4, x.detach(), G))

@@ -1,0 +1,70 @@
+"""GPU parity of the unit-vector and angular input interfaces and of the complex
+harmonics (paper Sections 2-3) against the oracle."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2510_05282_amd as sh
+from paper_2510_05282_amd import workloads
+
+pytestmark = pytest.mark.gpu
+LD = np.longdouble
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _units(n, seed, dtype):
+    p = workloads.isotropic_points(n, 1.0, 1.0, seed=seed).astype(LD)
+    return np.ascontiguousarray((p / np.sqrt((p * p).sum(1, keepdims=True))).astype(dtype))
+
+
+@pytest.mark.parametrize("n", [1, 7, 1000, 100003])
+def test_unit_interface(dev, orc, n):
+    for dtype, fn, tol in ((np.float64, sh.sh_eval_unit, 1e-13), (np.float32, sh.sh_eval_unit_f32, 5e-6)):
+        u = _units(n, 60 + n, dtype)
+        got = fn(9, torch.from_numpy(u).to(dev)).cpu().numpy()
+        # the oracle normalises; for points within rounding of the sphere the values agree
+        assert np.abs(got.astype(LD) - orc.eval_xyz(9, u)).max() <= tol
+
+
+def test_angles_interface(dev, orc):
+    rng = np.random.default_rng(61)
+    th = np.concatenate([np.arccos(rng.uniform(-1, 1, 50000)), [0.0, np.pi, np.pi / 2, 1e-9]])
+    ph = np.concatenate([rng.uniform(-np.pi, np.pi, 50000), [0.3, -2.0, 0.0, 1.0]])
+    got = sh.sh_eval_angles(9, torch.from_numpy(th).to(dev), torch.from_numpy(ph).to(dev)).cpu().numpy()
+    ref = orc.eval_angles(9, th.astype(LD), ph.astype(LD))
+    assert np.abs(got.astype(LD) - ref).max() <= 1e-13
+    th32, ph32 = th.astype(np.float32), ph.astype(np.float32)
+    got32 = sh.sh_eval_angles_f32(9, torch.from_numpy(th32).to(dev), torch.from_numpy(ph32).to(dev))
+    ref32 = orc.eval_angles(9, th32.astype(LD), ph32.astype(LD))
+    assert np.abs(got32.cpu().numpy().astype(LD) - ref32).max() <= 5e-6
+
+
+def test_appendix_d_points_on_gpu(dev, orc):
+    """The two Appendix D points through the angular interface on the GPU."""
+    th = np.array([2.12160245947564796, 1.69050041976591414])
+    ph = np.array([-1.82732370250979703, 0.758228122208986166])
+    got = sh.sh_eval_angles(9, torch.from_numpy(th).to(dev), torch.from_numpy(ph).to(dev)).cpu().numpy()
+    ref = orc.eval_angles(9, th.astype(LD), ph.astype(LD))
+    assert np.abs(got.astype(LD) - ref).max() <= 1e-14
+
+
+@pytest.mark.parametrize("lmax", [0, 1, 4, 9])
+def test_complex_harmonics(dev, orc, lmax):
+    pts = workloads.points_plain_eval(seed=2, n_random=20000)
+    got = sh.sh_eval_complex(lmax, torch.from_numpy(pts).to(dev)).cpu().numpy()
+    re, im = orc.eval_complex_xyz(lmax, pts)
+    assert np.abs(got.real.astype(LD) - re).max() <= 1e-13
+    assert np.abs(got.imag.astype(LD) - im).max() <= 1e-13
+    p32 = pts.astype(np.float32)
+    got32 = sh.sh_eval_complex_f32(lmax, torch.from_numpy(p32).to(dev)).cpu().numpy()
+    re32, im32 = orc.eval_complex_xyz(lmax, p32.astype(np.float64))
+    assert np.abs(got32.real.astype(LD) - re32).max() <= 5e-6
+    assert np.abs(got32.imag.astype(LD) - im32).max() <= 5e-6

@@ -268,3 +268,50 @@ def test_scale_invariance_and_f32_widening(orc):
     assert np.abs(Y1 - Y2).max() <= 1e-17
     p32 = pts.astype(np.float32)
     assert np.array_equal(orc.eval_xyz(9, p32), orc.eval_xyz(9, p32.astype(np.float64)))
+
+
+def test_complex_harmonics_mpmath_and_scipy(orc):
+    """Complex Y_l^m from the definition: mpmath spherharm (40 digits) and scipy
+    sph_harm_y, both carrying the Condon-Shortley phase."""
+    from scipy.special import sph_harm_y
+    mp.mp.dps = 40
+    pts = np.concatenate([workloads.isotropic_points(12, 0.1, 5.0, seed=51),
+                          np.array([[1e-8, 0, 1.0], [0.0, -2.0, 0.0]])])
+    re, im = orc.eval_complex_xyz(9, pts)
+    for i, (x, y, z) in enumerate(pts):
+        th, ph = _mp_angles(mp.mpf(x), mp.mpf(y), mp.mpf(z))
+        for l in range(10):
+            for m in range(-l, l + 1):
+                ref = mp.spherharm(l, m, th, ph)
+                r = _row(l, m)
+                assert abs(_mpf(re[r, i]) - mp.re(ref)) <= 2e-17
+                assert abs(_mpf(im[r, i]) - mp.im(ref)) <= 2e-17
+    big = workloads.isotropic_points(500, 0.1, 5.0, seed=52)
+    re, im = orc.eval_complex_xyz(9, big)
+    th = np.arccos(big[:, 2] / np.sqrt((big * big).sum(1)))
+    ph = np.arctan2(big[:, 1], big[:, 0])
+    for l in range(10):
+        for m in range(-l, l + 1):
+            ref = sph_harm_y(l, m, th, ph)
+            r = _row(l, m)
+            assert np.abs(re[r].astype(np.float64) - ref.real).max() <= 5e-14
+            assert np.abs(im[r].astype(np.float64) - ref.imag).max() <= 5e-14
+
+
+def test_complex_from_real_reading(orc):
+    """Y_l^m = (-1)^m (R_l^m + i R_l^-m) / sqrt(2) for m > 0; the relation as
+    printed in Section 3 (without 1/sqrt(2)) does not hold."""
+    pts = workloads.isotropic_points(200, 0.1, 5.0, seed=53)
+    R = orc.eval_xyz(9, pts)
+    re, im = orc.eval_complex_xyz(9, pts)
+    h = 1 / np.sqrt(LD(2))
+    worst = LD(0)
+    for l in range(10):
+        assert np.abs(re[_row(l, 0)] - R[_row(l, 0)]).max() <= 1e-18
+        for m in range(1, l + 1):
+            s = (-1) ** m
+            worst = max(worst, np.abs(re[_row(l, m)] - s * h * R[_row(l, m)]).max())
+            worst = max(worst, np.abs(im[_row(l, m)] - s * h * R[_row(l, -m)]).max())
+            printed = np.abs(re[_row(l, m)] - s * R[_row(l, m)]).max()
+            assert printed > 1e-3
+    assert worst <= 1e-18
