@@ -21,6 +21,32 @@ import sys
 import time
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+ROOT = os.path.dirname(os.path.abspath(__file__))
+FWD_SOURCES = ("sh_fwd.h", "sh_core.h", "sh_eval.hip", "sh_constants.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fwd_traffic.json")
+
+
+def fwd_source_hash() -> str:
+    """sha256 over the sources of the forward kernel (for matching counter data)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in FWD_SOURCES:
+        with open(os.path.join(ROOT, "paper_2510_05282_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the headline kernel from the committed rocprofv3
+    counter summary, or None when that summary was taken on other sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != fwd_source_hash():
+        return None
+    return t.get("traffic_bytes_per_launch")
 
 
 def _parse():
@@ -254,7 +280,8 @@ def main():
         "config": {"workload": "real Y_lm, lmax=9, FP64, 2^26 points, SoA [100][N] output",
                    "n_points": n, "lmax": 9},
         "roofline": {"bound": "hbm", "achieved": head["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": head["frac"], "traffic": None,
+                     "frac": head["frac"], "traffic": measured_traffic(),
+                     "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated)",
                      "kernel": "shk::fwd_kernel<9, double, 2>", "kernel_ms": head["kernel_ms"],
                      "bytes_per_point": head["bytes_per_point"]},
     }
