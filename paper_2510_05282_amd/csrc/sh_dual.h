@@ -110,7 +110,7 @@ __host__ __device__ __forceinline__ void grad_unit(T x, T y, T z, GetG&& g, T& v
             static_for<1, LMAX + 1>([&](auto lc) {
                 constexpr int L = decltype(lc)::value;
                 const D1 Z = zfac<D1, L, 0>(zd);
-                vz += g(row(L, 0)) * (K<T>::a(L, 0) * Z.d[0]);
+                vz += g(row(L, 0)) * (K<scalar_t<T>>::a(L, 0) * Z.d[0]);
             });
         } else {
             const D2 S = shat<D2, M>(xd, yd);
@@ -119,8 +119,8 @@ __host__ __device__ __forceinline__ void grad_unit(T x, T y, T z, GetG&& g, T& v
             static_for<M, LMAX + 1>([&](auto lc) {
                 constexpr int L = decltype(lc)::value;
                 const D1 Z = zfac<D1, L, M>(zd);
-                const T gs = g(row(L, -M)) * K<T>::a(L, M);
-                const T gc = g(row(L, M)) * K<T>::b(L, M);
+                const T gs = g(row(L, -M)) * K<scalar_t<T>>::a(L, M);
+                const T gc = g(row(L, M)) * K<scalar_t<T>>::b(L, M);
                 aS += gs * Z.v;
                 bS += gs * Z.d[0];
                 aC += gc * Z.v;
@@ -149,9 +149,9 @@ __host__ __device__ __forceinline__ void eval_unit_jac(T x, T y, T z, T keep, Si
             static_for<0, LMAX + 1>([&](auto lc) {
                 constexpr int L = decltype(lc)::value;
                 const D1 Z = zfac<D1, L, 0>(zd);
-                T v = K<T>::a(L, 0) * Z.v;
+                T v = K<scalar_t<T>>::a(L, 0) * Z.v;
                 if constexpr (L > 0 && L % 2 == 0) v *= keep;
-                sink(row(L, 0), v, T(0), T(0), K<T>::a(L, 0) * Z.d[0]);
+                sink(row(L, 0), v, T(0), T(0), K<scalar_t<T>>::a(L, 0) * Z.d[0]);
             });
         } else {
             const D2 S = shat<D2, M>(xd, yd);
@@ -159,8 +159,8 @@ __host__ __device__ __forceinline__ void eval_unit_jac(T x, T y, T z, T keep, Si
             static_for<M, LMAX + 1>([&](auto lc) {
                 constexpr int L = decltype(lc)::value;
                 const D1 Z = zfac<D1, L, M>(zd);
-                const T a = K<T>::a(L, M) * Z.v, ad = K<T>::a(L, M) * Z.d[0];
-                const T b = K<T>::b(L, M) * Z.v, bd = K<T>::b(L, M) * Z.d[0];
+                const T a = K<scalar_t<T>>::a(L, M) * Z.v, ad = K<scalar_t<T>>::a(L, M) * Z.d[0];
+                const T b = K<scalar_t<T>>::b(L, M) * Z.v, bd = K<scalar_t<T>>::b(L, M) * Z.d[0];
                 sink(row(L, -M), a * S.v, a * S.d[0], a * S.d[1], ad * S.v);
                 sink(row(L, M), b * C.v, b * C.d[0], b * C.d[1], bd * C.v);
             });

@@ -3,7 +3,8 @@
 //
 // A batch is a list of requests of any lmax and either dtype.  Each request is cut
 // into 256-point tiles; block b handles tile b of the batch, finds its request by
-// binary search over the requests' first-tile indices, and runs the same
+// a wave-parallel search over the requests' first-tile indices (64 lanes probe 64
+// evenly spaced entries per round, a ballot keeps the bracket), and runs the same
 // per-point projector evaluation as sh_projectors, dispatching once per block on
 // the request's (dtype, lmax).  Request descriptors travel host -> device through
 // a pinned staging buffer per slot (the slot is reused only after its previous
@@ -59,16 +60,28 @@ __device__ __forceinline__ void serve_dispatch(const ServeDesc& d, int64_t j)
     }
 }
 
-__global__ __launch_bounds__(256) void serve_kernel(const ServeDesc* __restrict__ descs, int n_items)
+// Last k in [0, n) with tile0[k] <= tile (tile0 increasing, tile0[0] = 0 <= tile).
+// Every lane of the wave returns the same k.
+__device__ __forceinline__ int find_item(const int64_t* __restrict__ tile0, int n, int64_t tile)
+{
+    const int lane = threadIdx.x & 63;
+    int lo = 0, hi = n;  // the answer lies in [lo, hi)
+    while (hi - lo > 1) {
+        const int step = (hi - lo + 63) / 64;
+        const int k = lo + lane * step;
+        const bool pred = k < hi && tile0[k] <= tile;
+        const int c = __popcll(__ballot(pred));  // lanes 0 .. c-1 hold entries <= tile
+        lo += (c - 1) * step;
+        hi = min(lo + step, hi);
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void serve_kernel(const ServeDesc* __restrict__ descs,
+                                                    const int64_t* __restrict__ tile0, int n_items)
 {
     const int64_t tile = blockIdx.x;
-    int lo = 0, hi = n_items - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (descs[mid].tile0 <= tile) lo = mid;
-        else hi = mid - 1;
-    }
-    const ServeDesc& d = descs[lo];
+    const ServeDesc& d = descs[find_item(tile0, n_items, tile)];
     const int64_t j = (tile - d.tile0) * 256 + threadIdx.x;
     if (j < 0 || j >= d.n) return;
     if (d.dtype == SH_F64) serve_dispatch<double>(d, j);
@@ -95,9 +108,8 @@ public:
         for (Slot& s : slots_) {
             if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||
                 hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess ||
-                hipHostMalloc(reinterpret_cast<void**>(&s.host), sizeof(shk::ServeDesc) * kMaxItems) !=
-                    hipSuccess ||
-                hipMalloc(&s.dev, sizeof(shk::ServeDesc) * kMaxItems) != hipSuccess) {
+                hipHostMalloc(reinterpret_cast<void**>(&s.host), kSlotBytes) != hipSuccess ||
+                hipMalloc(&s.dev, kSlotBytes) != hipSuccess) {
                 (void)hipGetLastError();
                 *status = SH_EHIP;
                 return;
@@ -123,6 +135,7 @@ public:
     int launch(int slot, const std::vector<Item>& items) override
     {
         Slot& s = slots_[slot];
+        int64_t* tile0 = reinterpret_cast<int64_t*>(s.host + kMaxItems);
         int64_t tiles = 0;
         for (size_t k = 0; k < items.size(); ++k) {
             const Item& it = items[k];
@@ -138,6 +151,7 @@ public:
             d.h2_over_6 = it.atom.h * it.atom.h / 6.0;
             d.n = it.atom.n;
             d.tile0 = tiles;
+            tile0[k] = tiles;
             d.n_r = it.atom.n_r;
             d.lmax = it.lmax;
             d.dtype = it.atom.dtype;
@@ -145,10 +159,14 @@ public:
         }
         if (items.empty()) return SH_OK;
         if (tiles > 0x7fffffff) return SH_EINVAL;
+        // descriptors, then the first-tile index array at a fixed offset
         hipError_t e = hipMemcpyAsync(s.dev, s.host, sizeof(shk::ServeDesc) * items.size(),
                                       hipMemcpyHostToDevice, s.stream);
+        int64_t* dev_tile0 = reinterpret_cast<int64_t*>(s.dev + kMaxItems);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(dev_tile0, tile0, sizeof(int64_t) * items.size(), hipMemcpyHostToDevice, s.stream);
         if (e == hipSuccess) {
-            hipLaunchKernelGGL(shk::serve_kernel, dim3(unsigned(tiles)), dim3(256), 0, s.stream, s.dev,
+            hipLaunchKernelGGL(shk::serve_kernel, dim3(unsigned(tiles)), dim3(256), 0, s.stream, s.dev, dev_tile0,
                                int(items.size()));
             e = hipGetLastError();
         }
@@ -166,6 +184,8 @@ public:
 
 private:
     static constexpr int64_t kMaxItems = 8192;
+    // per slot: kMaxItems descriptors followed by kMaxItems first-tile indices
+    static constexpr size_t kSlotBytes = (sizeof(shk::ServeDesc) + sizeof(int64_t)) * kMaxItems;
     struct Slot {
         hipStream_t stream = nullptr;
         hipEvent_t done = nullptr;

@@ -130,3 +130,29 @@ def test_autorelease_stream(dev):
     _say("  p50/p99 ms:", float(np.percentile(lat, 50)), float(np.percentile(lat, 99)))
     srv.close()
     radial.close()
+
+
+def test_large_mixed_batch_matches_projectors(dev):
+    """150 small requests submitted at once (one batch, so the kernel's request
+    search takes several rounds) against sh_projectors on each atom alone."""
+    reqs, pts, tabs = _requests(dev, 150, seed=6, n_hi=3e3)
+    radial = sh.Radial(tabs, 3.0)
+    srv = Server(1 << 30, n_slots=1)
+    atoms, dev_pts = _setup(dev, srv, reqs, pts, radial)
+    tickets = [srv.submit(a, r.lmax) for a, r in zip(atoms, reqs)]
+    for t in tickets:
+        assert srv.wait(t, 60) == DONE
+    _say("  batches:", srv.stats()["batches"])
+    for k, (t, r) in enumerate(zip(tickets, reqs)):
+        dt = torch.float64 if r.dtype == "f64" else torch.float32
+        got = srv.result(t, r.lmax, r.n, dt).double()
+        # FP64 projector of the same (widened) points and the same FP64 centre
+        toa = torch.tensor([k], dtype=torch.int32, device=dev)
+        ref = sh.sh_projectors(r.lmax, torch.tensor(np.asarray(r.center)[None], dtype=torch.float64, device=dev),
+                               torch.tensor([0, r.n], dtype=torch.int64, device=dev),
+                               dev_pts[k].double().contiguous(), radial, table_of_atom=toa)
+        tol = 1e-13 if r.dtype == "f64" else 5e-6
+        assert (got.reshape(-1) - ref).abs().max().item() <= tol, k
+        srv.release(t)
+    srv.close()
+    radial.close()
