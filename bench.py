@@ -116,6 +116,36 @@ def write_probe(buf, steps):
     return {"bytes": buf.numel() * buf.element_size(), "gbs": buf.numel() * buf.element_size() / avg / 1e9}
 
 
+def bench_interfaces(sh, xyz, out, steps):
+    """lmax 9 through the other interfaces on the same points: unit vectors (no
+    normalisation), angles (theta, phi), and complex output (2^25 points, 16 B
+    per value)."""
+    import torch
+    n = xyz.shape[0]
+    r = xyz.norm(dim=1, keepdim=True)
+    unit = (xyz / r).contiguous()
+    theta = torch.acos((xyz[:, 2:3] / r).clamp(-1, 1)).reshape(-1).contiguous()
+    phi = torch.atan2(xyz[:, 1], xyz[:, 0]).contiguous()
+    res = {}
+    o = out.view(-1)[: 100 * n].view(100, n)
+    for name, fn, inb in (("unit", lambda: sh.sh_eval_unit(9, unit, out=o), 24),
+                          ("angles", lambda: sh.sh_eval_angles(9, theta, phi, out=o), 16)):
+        _, per = time_launches(fn, steps, 2)
+        avg = sum(per) / len(per)
+        b = n * (inb + 800)
+        res[name] = {"points_per_s": n / avg, "kernel_ms": avg * 1e3, "gbs": b / avg / 1e9,
+                     "frac": b / avg / 1e9 / HBM_PEAK_GBS, "bytes_per_point": inb + 800}
+    nc = n // 2
+    oc = out.view(-1)[: 200 * nc].view(torch.complex128).view(100, nc)
+    xc = xyz[:nc].contiguous()
+    _, per = time_launches(lambda: sh.sh_eval_complex(9, xc, out=oc), steps, 2)
+    avg = sum(per) / len(per)
+    b = nc * (24 + 1600)
+    res["complex"] = {"n_points": nc, "points_per_s": nc / avg, "kernel_ms": avg * 1e3, "gbs": b / avg / 1e9,
+                      "frac": b / avg / 1e9 / HBM_PEAK_GBS, "bytes_per_point": 1624}
+    return res
+
+
 def bench_projectors(sh, workloads, dev, steps):
     """64 atoms, spheres of radius 3 on a 0.2 grid, lmax 3, 2000-knot tables."""
     import torch
@@ -148,11 +178,28 @@ def bench_gradient(sh, workloads, dev, steps):
     _, per_b = time_launches(lambda: sh.sh_eval_grad(lmax, x, G, grad_xyz=g), steps, 2)
     f, b = sum(per_f) / len(per_f), sum(per_b) / len(per_b)
     bf, bb = 24 + 49 * 8, 24 + 49 * 8 + 24
-    return {"workload": "2^24 points, lmax 6, FP64, forward + backward", "n_points": n,
-            "forward_ms": f * 1e3, "backward_ms": b * 1e3,
-            "forward_points_per_s": n / f, "backward_points_per_s": n / b,
-            "forward_gbs": n * bf / f / 1e9, "backward_gbs": n * bb / b / 1e9,
-            "backward_frac": n * bb / b / 1e9 / HBM_PEAK_GBS, "backward_bytes_per_point": bb}
+    res = {"workload": "2^24 points, lmax 6, FP64, forward + backward", "n_points": n,
+           "forward_ms": f * 1e3, "backward_ms": b * 1e3,
+           "forward_points_per_s": n / f, "backward_points_per_s": n / b,
+           "forward_gbs": n * bf / f / 1e9, "backward_gbs": n * bb / b / 1e9,
+           "backward_frac": n * bb / b / 1e9 / HBM_PEAK_GBS, "backward_bytes_per_point": bb}
+    # FP32 backward on the same points and upstream gradient, rounded
+    x32, G32, g32 = x.float(), G.float(), g.float()
+    _, per = time_launches(lambda: sh.sh_eval_grad_f32(lmax, x32, G32, grad_xyz=g32), steps, 2)
+    b32 = sum(per) / len(per)
+    res["backward_f32_ms"] = b32 * 1e3
+    res["backward_f32_points_per_s"] = n / b32
+    res["backward_f32_frac"] = n * 220 / b32 / 1e9 / HBM_PEAK_GBS
+    del x32, G32, g32, G
+    # fused values + Jacobian: 24 B in, 4 F 8 B out
+    jac = torch.empty((3, 49, n), dtype=torch.float64, device=dev)
+    _, per = time_launches(lambda: sh.sh_eval_jac(lmax, x, out=y, jac=jac), steps, 2)
+    j = sum(per) / len(per)
+    bj = 24 + 4 * 49 * 8
+    res["jacobian_ms"] = j * 1e3
+    res["jacobian_points_per_s"] = n / j
+    res["jacobian_frac"] = n * bj / j / 1e9 / HBM_PEAK_GBS
+    return res
 
 
 def bench_serving(sh, workloads, dev, n_req):
@@ -300,6 +347,9 @@ def main():
         result["write_probe"] = write_probe(out, 5)
         result["roofline"]["frac_of_write_probe"] = head["gbs"] / result["write_probe"]["gbs"]
         del xyz32
+        _log("interfaces")
+        result["interfaces"] = bench_interfaces(sh, xyz, out, max(5, args.steps // 2))
+        _log("  ", json.dumps(result["interfaces"]))
 
     del out
     torch.cuda.empty_cache()
