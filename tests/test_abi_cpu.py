@@ -103,3 +103,12 @@ def test_interface_variants_validation(L):
         assert getattr(L, fn)(10, 5, fake, fake, fake, None) == 1
         assert getattr(L, fn)(3, 5, fake, None, fake, None) == 1
         assert getattr(L, fn)(3, 0, None, None, None, None) == 0
+
+
+def test_missing_library_fails_loudly(tmp_path, monkeypatch):
+    """No fallback: without the built library every call raises."""
+    from paper_2510_05282_amd import _lib
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "absent.so"))
+    monkeypatch.setattr(_lib, "_lib", None)
+    with pytest.raises(ImportError):
+        _lib.lib()

@@ -217,3 +217,29 @@ def test_multi_launch_chunking(dev, orc):
                          idx_extra=np.arange(b - 300, b + 300))
     _ROOF.clear()
     assert err.max() <= TOL32
+
+
+def test_streams_and_threads(dev, orc):
+    """Calls are asynchronous on the caller's stream; two threads launching on two
+    streams get the same values as one launch on the default stream."""
+    import threading
+    pts = workloads.isotropic_points(200000, 0.1, 5.0, seed=70)
+    x = torch.from_numpy(pts).to(dev)
+    ref = sh.sh_eval(9, x).cpu()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    outs = {}
+
+    def work(k, s):
+        with torch.cuda.stream(s):
+            for _ in range(5):
+                outs[k] = sh.sh_eval(9, x, stream=s)
+            s.synchronize()
+
+    torch.cuda.synchronize()
+    th = [threading.Thread(target=work, args=(k, s)) for k, s in ((1, s1), (2, s2))]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert torch.equal(outs[1].cpu(), ref) and torch.equal(outs[2].cpu(), ref)
+    assert np.abs(ref.numpy()[:, :1000].astype(LD) - orc.eval_xyz(9, pts[:1000])).max() <= TOL64
