@@ -39,7 +39,8 @@
 extern "C" {
 #endif
 
-#define SH_LMAX 9 /* highest l with explicit formulas (paper, Section 3) */
+#define SH_LMAX 9      /* highest l with explicit formulas (paper, Section 3) */
+#define SH_LMAX_REC 24 /* highest l of sh_eval_rec */
 
 enum sh_status {
     SH_OK = 0,
@@ -80,6 +81,12 @@ int sh_eval_angles(int lmax, int64_t n, const double *theta, const double *phi, 
                    hipStream_t stream);
 int sh_eval_angles_f32(int lmax, int64_t n, const float *theta, const float *phi, float *out,
                        hipStream_t stream);
+
+/* Beyond l = 9 the paper points to recurrence relations (Conclusion):
+ * sh_eval_rec evaluates R_l^m for 0 <= lmax <= SH_LMAX_REC from the stable
+ * normalised associated-Legendre recurrence in z/r and (x + i y)^m / r^m, with the
+ * same normalisation, origin guard and [F][n] layout as sh_eval (double). */
+int sh_eval_rec(int lmax, int64_t n, const double *xyz, double *out, hipStream_t stream);
 
 /* Complex harmonics Y_l^m (eq. sphericalfromlegendre, with the Condon-Shortley
  * phase), built from the real ones (Section 3): Y_l^0 = R_l^0 and, for m > 0,

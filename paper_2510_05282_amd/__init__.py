@@ -16,13 +16,14 @@ import torch
 from ._lib import ShError, check, lib
 
 SH_LMAX = 9
+SH_LMAX_REC = 24
 SH_F64 = 0
 SH_F32 = 1
 
 __all__ = ["SH_LMAX", "Radial", "ShError", "SphericalHarmonics", "nfun", "row", "sh_eval",
            "sh_eval_angles", "sh_eval_angles_f32", "sh_eval_complex", "sh_eval_complex_f32",
            "sh_eval_f32", "sh_eval_grad", "sh_eval_grad_f32", "sh_eval_jac", "sh_eval_ld",
-           "sh_eval_unit", "sh_eval_unit_f32",
+           "sh_eval_rec", "sh_eval_unit", "sh_eval_unit_f32",
            "sh_projectors", "sh_projectors_f32", "sh_radial_create", "sh_radial_destroy",
            "sh_strerror", "spherical_harmonics"]
 
@@ -100,6 +101,11 @@ def sh_eval_f32(lmax: int, xyz: torch.Tensor, out: torch.Tensor | None = None,
                 stream=None) -> torch.Tensor:
     """Single-precision twin of sh_eval (normalisation still in FP64)."""
     return _eval("sh_eval_f32", torch.float32, lmax, xyz, out, stream)
+
+
+def sh_eval_rec(lmax: int, xyz: torch.Tensor, out: torch.Tensor | None = None, stream=None):
+    """Real harmonics for lmax <= 24 by recurrence (float64), layout as sh_eval."""
+    return _eval("sh_eval_rec", torch.float64, lmax, xyz, out, stream)
 
 
 def sh_eval_unit(lmax: int, xyz: torch.Tensor, out: torch.Tensor | None = None, stream=None):

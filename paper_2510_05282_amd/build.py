@@ -16,7 +16,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libshmi.so")
-SOURCES = ["sh_api.hip", "sh_eval.hip", "sh_grad.hip", "sh_proj.hip", "sh_serve.hip",
+SOURCES = ["sh_api.hip", "sh_eval.hip", "sh_grad.hip", "sh_proj.hip", "sh_rec.hip", "sh_serve.hip",
            "sh_server.cpp"]
 ARCH = "gfx950"
 

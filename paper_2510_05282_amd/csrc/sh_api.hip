@@ -130,6 +130,14 @@ int sh_eval_complex_f32(int lmax, int64_t n, const float *xyz, float *out, hipSt
     return eval_complex<float>(lmax, n, xyz, out, stream);
 }
 
+int sh_eval_rec(int lmax, int64_t n, const double *xyz, double *out, hipStream_t stream)
+{
+    if (lmax < 0 || lmax > SH_LMAX_REC || n < 0) return SH_EINVAL;
+    if (n == 0) return SH_OK;
+    if (!xyz || !out) return SH_EINVAL;
+    return hip_status(shk::launch_rec(lmax, n, xyz, out, n, stream));
+}
+
 int sh_eval(int lmax, int64_t n, const double *xyz, double *out, hipStream_t stream)
 {
     return sh_eval_ld(lmax, n, xyz, out, n, SH_F64, stream);

@@ -63,3 +63,13 @@ extern "C" void core_jac9(long n, const double *u, double *val, double *jac)
         });
     }
 }
+
+#include "../../paper_2510_05282_amd/csrc/sh_rec.h"
+
+// Recurrence core at unit vectors: out[(lmax+1)^2][n].
+extern "C" void core_rec(long n, const double *u, int lmax, double *out)
+{
+    for (long i = 0; i < n; ++i)
+        shk::eval_unit_rec(u[3 * i], u[3 * i + 1], u[3 * i + 2], 1.0, lmax,
+                           [&](int r, double v) { out[r * n + i] = v; });
+}

@@ -112,3 +112,11 @@ def test_missing_library_fails_loudly(tmp_path, monkeypatch):
     monkeypatch.setattr(_lib, "_lib", None)
     with pytest.raises(ImportError):
         _lib.lib()
+
+
+def test_rec_validation(L):
+    fake = ctypes.c_void_p(0x1000)
+    assert L.sh_eval_rec(25, 5, fake, fake, None) == 1
+    assert L.sh_eval_rec(-1, 5, fake, fake, None) == 1
+    assert L.sh_eval_rec(24, 5, None, fake, None) == 1
+    assert L.sh_eval_rec(24, 0, None, None, None) == 0

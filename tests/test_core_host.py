@@ -114,3 +114,14 @@ def test_core_values_and_jacobian(core, orc):
     assert np.abs(val.astype(LD) - orc.eval_xyz(9, u)).max() <= 3e-14
     J = orc.jacobian_xyz(9, u)
     assert np.abs(jac.astype(LD) - J).max() <= 1e-12 * (1 + float(np.abs(J).max()))
+
+
+@pytest.mark.parametrize("lmax", [0, 1, 9, 16, 24])
+def test_core_recurrence(core, orc, lmax):
+    core.core_rec.argtypes = [ctypes.c_long, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]
+    u = _units(_pts()[:20000], np.float64)
+    F = (lmax + 1) ** 2
+    out = np.empty((F, u.shape[0]))
+    core.core_rec(u.shape[0], u.ctypes.data, lmax, out.ctypes.data)
+    err = np.abs(out.astype(LD) - orc.eval_xyz(lmax, u)).max()
+    assert err <= 1e-13, err

@@ -68,3 +68,13 @@ def test_complex_harmonics(dev, orc, lmax):
     re32, im32 = orc.eval_complex_xyz(lmax, p32.astype(np.float64))
     assert np.abs(got32.real.astype(LD) - re32).max() <= 5e-6
     assert np.abs(got32.imag.astype(LD) - im32).max() <= 5e-6
+
+
+@pytest.mark.parametrize("lmax", [0, 5, 9, 12, 18, 24])
+def test_recurrence_beyond_l9(dev, orc, lmax):
+    pts = workloads.points_plain_eval(seed=3, n_random=20000)
+    got = sh.sh_eval_rec(lmax, torch.from_numpy(pts).to(dev)).cpu().numpy()
+    assert np.abs(got.astype(LD) - orc.eval_xyz(lmax, pts)).max() <= 1e-13
+    if lmax <= 9:  # agrees with the explicit formulas
+        ex = sh.sh_eval(lmax, torch.from_numpy(pts).to(dev)).cpu().numpy()
+        assert np.abs(got - ex).max() <= 2e-14

@@ -315,3 +315,35 @@ def test_complex_from_real_reading(orc):
             printed = np.abs(re[_row(l, m)] - s * R[_row(l, m)]).max()
             assert printed > 1e-3
     assert worst <= 1e-18
+
+
+def test_high_l_mpmath_addition_and_quadrature(orc):
+    """Beyond l = 9 (the recurrence interface goes to l = 24): mpmath at 40 digits
+    for l = 12, 17, 24, the addition theorem for every l <= 24, and exact
+    Gauss-Legendre x uniform-phi orthonormality up to l = 24."""
+    mp.mp.dps = 40
+    L = 24
+    pts = np.concatenate([workloads.isotropic_points(6, 0.1, 5.0, seed=81),
+                          np.array([[1e-8, 2e-8, 1.0], [0.0, -3.0, 1e-9]])])
+    Y = orc.eval_xyz(L, pts)
+    for i, (x, y, z) in enumerate(pts):
+        th, ph = _mp_angles(mp.mpf(x), mp.mpf(y), mp.mpf(z))
+        for l in (12, 17, 24):
+            for m in range(-l, l + 1, 5):
+                ref = _mp_real_ylm(l, m, th, ph)
+                assert abs(_mpf(Y[_row(l, m), i]) - ref) <= 1e-16, (l, m)
+    big = workloads.isotropic_points(500, 0.1, 5, seed=82)
+    Yb = orc.eval_xyz(L, big)
+    for l in range(L + 1):
+        s = (Yb[l * l:(l + 1) * (l + 1)] ** 2).sum(axis=0)
+        ref = LD(2 * l + 1) / (4 * PI_LD)
+        assert (np.abs(s - ref) / ref).max() <= 1e-16
+    xg, wg = np.polynomial.legendre.leggauss(L + 1)
+    nphi = 2 * L + 1
+    phis = 2 * np.pi * np.arange(nphi) / nphi
+    th = np.repeat(np.arccos(xg), nphi)
+    ph = np.tile(phis, L + 1)
+    w = np.repeat(wg, nphi) * (2 * np.pi / nphi)
+    Yq = orc.eval_angles(L, th.astype(LD), ph.astype(LD)).astype(np.float64)
+    G = (Yq * w) @ Yq.T
+    assert np.abs(G - np.eye((L + 1) ** 2)).max() <= 1e-13
