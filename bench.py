@@ -118,8 +118,8 @@ def write_probe(buf, steps):
 
 def bench_interfaces(sh, xyz, out, steps):
     """lmax 9 through the other interfaces on the same points: unit vectors (no
-    normalisation), angles (theta, phi), and complex output (2^25 points, 16 B
-    per value)."""
+    normalisation), angles (theta, phi), complex output (2^25 points, 16 B
+    per value) and spinor output (2^23 points, 400 complex values each)."""
     import torch
     n = xyz.shape[0]
     r = xyz.norm(dim=1, keepdim=True)
@@ -143,6 +143,15 @@ def bench_interfaces(sh, xyz, out, steps):
     b = nc * (24 + 1600)
     res["complex"] = {"n_points": nc, "points_per_s": nc / avg, "kernel_ms": avg * 1e3, "gbs": b / avg / 1e9,
                       "frac": b / avg / 1e9 / HBM_PEAK_GBS, "bytes_per_point": 1624}
+    # spinors: 200 (l, j, m_j) x 2 components x 16 B per point
+    ns = n // 8
+    os_ = out.view(-1)[: 800 * ns].view(torch.complex128).view(200, 2, ns)
+    xs = xyz[:ns].contiguous()
+    _, per = time_launches(lambda: sh.sh_eval_spinor(9, xs, out=os_), steps, 2)
+    avg = sum(per) / len(per)
+    b = ns * (24 + 6400)
+    res["spinor"] = {"n_points": ns, "points_per_s": ns / avg, "kernel_ms": avg * 1e3, "gbs": b / avg / 1e9,
+                     "frac": b / avg / 1e9 / HBM_PEAK_GBS, "bytes_per_point": 6424}
     return res
 
 

@@ -97,6 +97,22 @@ int sh_eval_rec(int lmax, int64_t n, const double *xyz, double *out, hipStream_t
 int sh_eval_complex(int lmax, int64_t n, const double *xyz, double *out, hipStream_t stream);
 int sh_eval_complex_f32(int lmax, int64_t n, const float *xyz, float *out, hipStream_t stream);
 
+/* Spinor harmonics for spin 1/2 (eq. spinorial), built from the complex ones as
+ * in Section 3: for orbital l and total j = l + 1/2 (l >= 0) or j = l - 1/2
+ * (l >= 1), with m_j = -j .. j,
+ *   j = l + 1/2:  upper =  sqrt((l + m_j + 1/2)/(2l+1)) Y_l^{m_j-1/2},
+ *                 lower =  sqrt((l - m_j + 1/2)/(2l+1)) Y_l^{m_j+1/2},
+ *   j = l - 1/2:  upper = -sqrt((l - m_j + 1/2)/(2l+1)) Y_l^{m_j-1/2},
+ *                 lower =  sqrt((l + m_j + 1/2)/(2l+1)) Y_l^{m_j+1/2},
+ * with Y_l^m = 0 for |m| > l.  Spinors are numbered l-major, j = l - 1/2 before
+ * j = l + 1/2, m_j ascending: k = 2l^2 + (m_j + l - 1/2) for j = l - 1/2 and
+ * k = 2l^2 + 2l + (m_j + l + 1/2) for j = l + 1/2, so there are 2 (lmax+1)^2 of
+ * them.  out is [2 (lmax+1)^2][2][n] complex values, (re, im) pairs, component
+ * 0 the upper (spin-up) one: 4 (lmax+1)^2 n complex values in all.  Arguments,
+ * validation and origin convention as sh_eval_complex. */
+int sh_eval_spinor(int lmax, int64_t n, const double *xyz, double *out, hipStream_t stream);
+int sh_eval_spinor_f32(int lmax, int64_t n, const float *xyz, float *out, hipStream_t stream);
+
 /* Backward pass of sh_eval (vector-Jacobian product), for forces:
  *   grad_xyz[i][k] = sum_{row} grad_out[row][i] * d R_row(x_i) / d x_{i,k}
  * with xyz [n][3], grad_out [F][n] and grad_xyz [n][3], all double.  The

@@ -110,6 +110,55 @@ def eval_complex_xyz(lmax: int, xyz):
     return re, im
 
 
+def spinor_index(l: int, kappa: int, twice_mj: int) -> int:
+    """Index of the spinor harmonic with orbital l, j = l + kappa/2 (kappa = +1 or -1)
+    and m_j = twice_mj / 2: l-major, j = l - 1/2 before j = l + 1/2, m_j ascending."""
+    base = 2 * l * l
+    if kappa < 0:
+        return base + (twice_mj + 2 * l - 1) // 2
+    return base + 2 * l + (twice_mj + 2 * l + 1) // 2
+
+
+def eval_spinor_xyz(lmax: int, xyz):
+    """Spinor harmonics (paper eq. spinorial) from the complex definition, for
+    l <= lmax: returns (re, im), each [2 (lmax+1)^2][2][n] long double, component 0
+    the upper (spin up) one.  For j = l + 1/2 and j = l - 1/2 (l >= 1):
+        upper = +- sqrt(l +- m_j + 1/2) Y_l^{m_j - 1/2} / sqrt(2l + 1)
+        lower =    sqrt(l -+ m_j + 1/2) Y_l^{m_j + 1/2} / sqrt(2l + 1)
+    with Y_l^m = 0 for |m| > l."""
+    re_y, im_y = eval_complex_xyz(lmax, xyz)
+    n = re_y.shape[1]
+    ns = 2 * (lmax + 1) ** 2
+    re = np.zeros((ns, 2, n), dtype=LD)
+    im = np.zeros((ns, 2, n), dtype=LD)
+
+    def y(l, m2):  # m2 = 2m (odd m_j +- 1/2 -> integer m)
+        m = m2 // 2
+        if abs(m) > l:
+            return np.zeros(n, dtype=LD), np.zeros(n, dtype=LD)
+        return re_y[l * l + l + m], im_y[l * l + l + m]
+
+    for l in range(lmax + 1):
+        den = np.sqrt(LD(2 * l + 1))
+        for kappa in (-1, 1):
+            if kappa < 0 and l == 0:
+                continue
+            j2 = 2 * l + kappa
+            for mj2 in range(-j2, j2 + 1, 2):
+                k = spinor_index(l, kappa, mj2)
+                ur, ui = y(l, mj2 - 1)
+                lr, li = y(l, mj2 + 1)
+                if kappa > 0:
+                    cu = np.sqrt(LD(2 * l + mj2 + 1) / 2) / den
+                    cl = np.sqrt(LD(2 * l - mj2 + 1) / 2) / den
+                else:
+                    cu = -np.sqrt(LD(2 * l - mj2 + 1) / 2) / den
+                    cl = np.sqrt(LD(2 * l + mj2 + 1) / 2) / den
+                re[k, 0], im[k, 0] = cu * ur, cu * ui
+                re[k, 1], im[k, 1] = cl * lr, cl * li
+    return re, im
+
+
 def eval_angles(lmax: int, theta, phi) -> np.ndarray:
     """Real harmonics at polar angle theta and azimuth phi; returns [F][n] long double."""
     t = np.ascontiguousarray(np.atleast_1d(theta), dtype=LD)

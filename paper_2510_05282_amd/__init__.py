@@ -22,6 +22,7 @@ SH_F32 = 1
 
 __all__ = ["SH_LMAX", "Radial", "ShError", "SphericalHarmonics", "nfun", "row", "sh_eval",
            "sh_eval_angles", "sh_eval_angles_f32", "sh_eval_complex", "sh_eval_complex_f32",
+           "sh_eval_spinor", "sh_eval_spinor_f32", "spinor_index",
            "sh_eval_f32", "sh_eval_grad", "sh_eval_grad_f32", "sh_eval_jac", "sh_eval_ld",
            "sh_eval_rec", "sh_eval_unit", "sh_eval_unit_f32",
            "sh_projectors", "sh_projectors_f32", "sh_radial_create", "sh_radial_destroy",
@@ -164,6 +165,39 @@ def sh_eval_complex(lmax: int, xyz: torch.Tensor, out=None, stream=None) -> torc
 def sh_eval_complex_f32(lmax: int, xyz: torch.Tensor, out=None, stream=None) -> torch.Tensor:
     """Complex harmonics [F, n] (complex64) of float32 points."""
     return _complex("sh_eval_complex_f32", torch.float32, torch.complex64, lmax, xyz, out, stream)
+
+
+def spinor_index(l: int, twice_j: int, twice_mj: int) -> int:
+    """Row of the spinor harmonic (l, j = twice_j/2, m_j = twice_mj/2) in the
+    output of sh_eval_spinor: l-major, j = l - 1/2 before j = l + 1/2, m_j ascending."""
+    if twice_j == 2 * l + 1:
+        return 2 * l * l + 2 * l + (twice_mj + 2 * l + 1) // 2
+    if twice_j == 2 * l - 1 and l >= 1:
+        return 2 * l * l + (twice_mj + 2 * l - 1) // 2
+    raise ValueError(f"no spinor harmonic with l={l}, 2j={twice_j}")
+
+
+def _spinor(fn, dtype, ctype, lmax, xyz, out, stream):
+    n = _points(xyz, dtype)
+    S = 2 * (lmax + 1) ** 2
+    if out is None:
+        out = torch.empty((S, 2, n), dtype=ctype, device=xyz.device)
+    elif out.dtype != ctype or tuple(out.shape) != (S, 2, n) or not out.is_contiguous():
+        raise ValueError(f"out must be a contiguous [{S}, 2, {n}] {ctype} tensor")
+    with torch.cuda.device(xyz.device):
+        check(fn, getattr(lib(), fn)(lmax, n, xyz.data_ptr(), out.data_ptr(), _stream(xyz.device, stream)))
+    return out
+
+
+def sh_eval_spinor(lmax: int, xyz: torch.Tensor, out=None, stream=None) -> torch.Tensor:
+    """Spin-1/2 spinor harmonics [2 (lmax+1)^2, 2, n] (complex128) of float64 points;
+    the middle index is the spin component (0 = up)."""
+    return _spinor("sh_eval_spinor", torch.float64, torch.complex128, lmax, xyz, out, stream)
+
+
+def sh_eval_spinor_f32(lmax: int, xyz: torch.Tensor, out=None, stream=None) -> torch.Tensor:
+    """Spinor harmonics [2 (lmax+1)^2, 2, n] (complex64) of float32 points."""
+    return _spinor("sh_eval_spinor_f32", torch.float32, torch.complex64, lmax, xyz, out, stream)
 
 
 def _grad(fn: str, dtype, lmax, xyz, grad_out, grad_xyz, stream):

@@ -29,6 +29,15 @@ int hip_status(hipError_t e)
 bool bad_lmax(int lmax) { return lmax < 0 || lmax > SH_LMAX; }
 
 template <typename TIO>
+static int eval_spinor(int lmax, int64_t n, const TIO *xyz, TIO *out, hipStream_t stream)
+{
+    if (bad_lmax(lmax) || n < 0) return SH_EINVAL;
+    if (n == 0) return SH_OK;
+    if (!xyz || !out) return SH_EINVAL;
+    return hip_status(shk::launch_fwd_spinor<TIO>(lmax, n, xyz, out, n, stream));
+}
+
+template <typename TIO>
 static int eval_unit(int lmax, int64_t n, const TIO *xyz, TIO *out, hipStream_t stream)
 {
     if (bad_lmax(lmax) || n < 0) return SH_EINVAL;
@@ -128,6 +137,16 @@ int sh_eval_complex(int lmax, int64_t n, const double *xyz, double *out, hipStre
 int sh_eval_complex_f32(int lmax, int64_t n, const float *xyz, float *out, hipStream_t stream)
 {
     return eval_complex<float>(lmax, n, xyz, out, stream);
+}
+
+int sh_eval_spinor(int lmax, int64_t n, const double *xyz, double *out, hipStream_t stream)
+{
+    return eval_spinor<double>(lmax, n, xyz, out, stream);
+}
+
+int sh_eval_spinor_f32(int lmax, int64_t n, const float *xyz, float *out, hipStream_t stream)
+{
+    return eval_spinor<float>(lmax, n, xyz, out, stream);
 }
 
 int sh_eval_rec(int lmax, int64_t n, const double *xyz, double *out, hipStream_t stream)

@@ -147,6 +147,69 @@ __host__ __device__ __forceinline__ void eval_unit(T x, T y, T z, T keep, Sink&&
     });
 }
 
+// Complex harmonics Y_l^m with the Condon-Shortley phase, from the real ones
+// (Section 3): Y_l^0 = R_l^0 and, for m > 0,
+//     Y_l^m = (-1)^m (R_l^m + i R_l^-m) / sqrt(2),   Y_l^-m = (R_l^m - i R_l^-m) / sqrt(2).
+// sink(l, m, re, im) receives each one; +m and -m are formed together as soon as
+// R_l^-m and R_l^m (which eval_unit delivers back to back) are both known.
+template <int LMAX, typename T, typename Sink>
+__host__ __device__ __forceinline__ void complex_unit(T x, T y, T z, T keep, Sink&& sink)
+{
+    const T h = T(scalar_t<T>(0.70710678118654752440));  // 1/sqrt(2)
+    T sin_part = T(scalar_t<T>(0));
+    eval_unit<LMAX, T>(x, y, z, keep, [&](int r, T v) {
+        int l = 0;
+        while ((l + 1) * (l + 1) <= r) ++l;
+        const int m = r - l * l - l;
+        if (m == 0) {
+            sink(l, 0, v, T(scalar_t<T>(0)));
+        } else if (m < 0) {
+            sin_part = v;  // R_l^-|m| arrives just before R_l^|m|
+        } else {
+            const T re = h * v, im = h * sin_part;
+            if (m & 1) sink(l, m, -re, -im);
+            else sink(l, m, re, im);
+            sink(l, -m, re, -im);
+        }
+    });
+}
+
+// Spin-1/2 spinor harmonics (eq. spinorial) from the complex ones.  For orbital
+// l and total j = l +- 1/2,
+//     j = l + 1/2: upper =  sqrt((l + m_j + 1/2)/(2l+1)) Y_l^{m_j-1/2}, lower = sqrt((l - m_j + 1/2)/(2l+1)) Y_l^{m_j+1/2}
+//     j = l - 1/2: upper = -sqrt((l - m_j + 1/2)/(2l+1)) Y_l^{m_j-1/2}, lower = sqrt((l + m_j + 1/2)/(2l+1)) Y_l^{m_j+1/2}
+// with Y_l^m = 0 for |m| > l.  Each Y_l^m therefore feeds at most four
+// components with fixed coefficients and is passed on as soon as it is formed.
+// Spinor index k (l-major; j = l - 1/2 first; m_j ascending):
+//     j = l - 1/2: k = 2l^2 + (m_j + l - 1/2),   j = l + 1/2: k = 2l^2 + 2l + (m_j + l + 1/2).
+// sink(k, c, re, im) receives component c (0 = upper) of spinor k; every (k, c)
+// of l <= LMAX is delivered exactly once, the structural zeros included.
+template <int LMAX, typename T, typename Sink>
+__host__ __device__ __forceinline__ void spinor_unit(T x, T y, T z, T keep, Sink&& sink)
+{
+    using S = scalar_t<T>;
+    complex_unit<LMAX, T>(x, y, z, keep, [&](int l, int m, T re, T im) {
+        const S inv = S(1) / S(2 * l + 1);
+        const int base = 2 * l * l;
+        // j = l + 1/2: upper of m_j = m + 1/2, lower of m_j = m - 1/2
+        const T cu = T(S(sqrt(double(l + m + 1) * double(inv))));
+        const T cl = T(S(sqrt(double(l - m + 1) * double(inv))));
+        sink(base + 2 * l + l + m + 1, 0, cu * re, cu * im);
+        sink(base + 2 * l + l + m, 1, cl * re, cl * im);
+        if (m <= l - 1) {  // j = l - 1/2, upper of m_j = m + 1/2
+            const T c = T(S(-sqrt(double(l - m) * double(inv))));
+            sink(base + l + m, 0, c * re, c * im);
+        }
+        if (m >= 1 - l) {  // j = l - 1/2, lower of m_j = m - 1/2
+            const T c = T(S(sqrt(double(l + m) * double(inv))));
+            sink(base + l + m - 1, 1, c * re, c * im);
+        }
+        const T zero = T(S(0));
+        if (m == l) sink(base + 4 * l + 1, 1, zero, zero);  // j = l + 1/2, m_j = l + 1/2
+        if (m == -l) sink(base + 2 * l, 0, zero, zero);     // j = l + 1/2, m_j = -l - 1/2
+    });
+}
+
 // 1/sqrt(a) for a > 0: the hardware estimate (v_rsq_f64) refined by two Newton
 // steps y <- y + y (1 - a y^2) / 2, each evaluated with fused multiply-adds.
 __device__ __forceinline__ double rsqrt_refined(double a)

@@ -143,6 +143,41 @@ hipError_t launch_fwd_complex(int lmax, int64_t n, const TIO* xyz, TIO* out, int
     }
 }
 
+template <int LMAX, typename TIO>
+static hipError_t launch_spinor_l(int64_t n, const TIO* xyz, TIO* out, int64_t ld, hipStream_t s)
+{
+    const size_t lds = sizeof(TIO) == 8 ? kCapLds : 0;
+    for (int64_t c0 = 0; c0 < n; c0 += kChunk) {
+        const int64_t nc = n - c0 < kChunk ? n - c0 : kChunk;
+        const unsigned grid = unsigned((nc + kFwdBlock - 1) / kFwdBlock);
+        hipLaunchKernelGGL((fwd_spinor_kernel<LMAX, TIO>), dim3(grid), dim3(kFwdBlock), lds, s, xyz + 3 * c0,
+                           out + 2 * c0, uint32_t(nc), ld);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <typename TIO>
+hipError_t launch_fwd_spinor(int lmax, int64_t n, const TIO* xyz, TIO* out, int64_t ld, hipStream_t s)
+{
+    switch (lmax) {
+    case 0: return launch_spinor_l<0, TIO>(n, xyz, out, ld, s);
+    case 1: return launch_spinor_l<1, TIO>(n, xyz, out, ld, s);
+    case 2: return launch_spinor_l<2, TIO>(n, xyz, out, ld, s);
+    case 3: return launch_spinor_l<3, TIO>(n, xyz, out, ld, s);
+    case 4: return launch_spinor_l<4, TIO>(n, xyz, out, ld, s);
+    case 5: return launch_spinor_l<5, TIO>(n, xyz, out, ld, s);
+    case 6: return launch_spinor_l<6, TIO>(n, xyz, out, ld, s);
+    case 7: return launch_spinor_l<7, TIO>(n, xyz, out, ld, s);
+    case 8: return launch_spinor_l<8, TIO>(n, xyz, out, ld, s);
+    case 9: return launch_spinor_l<9, TIO>(n, xyz, out, ld, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template hipError_t launch_fwd_spinor<double>(int, int64_t, const double*, double*, int64_t, hipStream_t);
+template hipError_t launch_fwd_spinor<float>(int, int64_t, const float*, float*, int64_t, hipStream_t);
 template hipError_t launch_fwd<double>(int, int64_t, const double*, double*, int64_t, hipStream_t);
 template hipError_t launch_fwd<float>(int, int64_t, const float*, float*, int64_t, hipStream_t);
 template hipError_t launch_fwd_unit<double>(int, int64_t, const double*, double*, int64_t, hipStream_t);

@@ -121,21 +121,30 @@ __global__ __launch_bounds__(kFwdBlock) void fwd_complex_kernel(const TIO* __res
         v.y = im;
         *reinterpret_cast<C*>(reinterpret_cast<char*>(reinterpret_cast<C*>(out) + int64_t(r) * ld) + boff) = v;
     };
-    const TIO h = TIO(0.70710678118654752440);  // 1/sqrt(2)
-    TIO sin_part = TIO(0);
-    eval_unit<LMAX, TIO>(TIO(xb), TIO(yb), TIO(zb), TIO(kb), [&](int r, TIO v) {
-        int l = 0;
-        while ((l + 1) * (l + 1) <= r) ++l;
-        const int m = r - l * l - l;
-        if (m == 0) {
-            store(r, v, TIO(0));
-        } else if (m < 0) {
-            sin_part = v;  // R_l^-|m| arrives just before R_l^|m|
-        } else {
-            const TIO re = h * v, im = h * sin_part;
-            store(r, (m & 1) ? -re : re, (m & 1) ? -im : im);
-            store(l * l + l - m, re, -im);
-        }
+    complex_unit<LMAX, TIO>(TIO(xb), TIO(yb), TIO(zb), TIO(kb),
+                            [&](int l, int m, TIO re, TIO im) { store(row(l, m), re, im); });
+}
+
+// Spinor harmonics (eq. spinorial): spinor_unit's values, stored as they come to
+// out[(2 k + c) ld + i] as (re, im) pairs (c = 0 for the upper component).  One
+// complex value per lane and row, like the complex kernel.
+template <int LMAX, typename TIO>
+__global__ __launch_bounds__(kFwdBlock) void fwd_spinor_kernel(const TIO* __restrict__ xyz,
+                                                               TIO* __restrict__ out, uint32_t n, int64_t ld)
+{
+    using C = typename vec_of<TIO, 2>::type;
+    const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t i = b * kFwdBlock + threadIdx.x;
+    if (i >= n) return;
+    double xb, yb, zb, kb;
+    load_unit<In::kXyz, TIO>(xyz, nullptr, i, xb, yb, zb, kb);
+    const uint32_t boff = i * uint32_t(sizeof(C));
+    spinor_unit<LMAX, TIO>(TIO(xb), TIO(yb), TIO(zb), TIO(kb), [&](int k, int c, TIO re, TIO im) {
+        C v;
+        v.x = re;
+        v.y = im;
+        *reinterpret_cast<C*>(reinterpret_cast<char*>(reinterpret_cast<C*>(out) + int64_t(2 * k + c) * ld) +
+                              boff) = v;
     });
 }
 

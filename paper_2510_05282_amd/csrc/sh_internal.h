@@ -33,6 +33,10 @@ hipError_t launch_fwd_complex(int lmax, int64_t n, const TIO* xyz, TIO* out, int
 template <typename TIO>
 hipError_t launch_grad(int lmax, int64_t n, const TIO* xyz, const TIO* G, int64_t ldg, TIO* gxyz, hipStream_t s);
 
+// Spinor harmonics into out[2 (lmax+1)^2][2][ld] of (re, im) pairs.
+template <typename TIO>
+hipError_t launch_fwd_spinor(int lmax, int64_t n, const TIO* xyz, TIO* out, int64_t ld, hipStream_t s);
+
 // Real harmonics up to lmax <= SH_LMAX_REC by recurrence (FP64).
 hipError_t launch_rec(int lmax, int64_t n, const double* xyz, double* out, int64_t ld, hipStream_t s);
 

@@ -73,3 +73,41 @@ extern "C" void core_rec(long n, const double *u, int lmax, double *out)
         shk::eval_unit_rec(u[3 * i], u[3 * i + 1], u[3 * i + 2], 1.0, lmax,
                            [&](int r, double v) { out[r * n + i] = v; });
 }
+
+// Complex and spinor cores at unit vectors: (re, im) pairs, out[rows][n][2] with
+// rows = (lmax+1)^2 complex values, or 2 (lmax+1)^2 spinors x 2 components.
+// Every entry of `out` must be written once: the caller fills it with NaN first.
+extern "C" void core_complex9(long n, const double *u, double *out)
+{
+    for (long i = 0; i < n; ++i)
+        shk::complex_unit<9, double>(u[3 * i], u[3 * i + 1], u[3 * i + 2], 1.0,
+                                     [&](int l, int m, double re, double im) {
+                                         double *o = out + 2 * (long(shk::row(l, m)) * n + i);
+                                         o[0] = re;
+                                         o[1] = im;
+                                     });
+}
+
+template <int LMAX>
+static void spinor(long n, const double *u, double *out, int *count)
+{
+    for (long i = 0; i < n; ++i)
+        shk::spinor_unit<LMAX, double>(u[3 * i], u[3 * i + 1], u[3 * i + 2], 1.0,
+                                       [&](int k, int c, double re, double im) {
+                                           const long e = (long(2 * k + c) * n + i);
+                                           out[2 * e] = re;
+                                           out[2 * e + 1] = im;
+                                           count[e] += 1;
+                                       });
+}
+
+extern "C" void core_spinor(long n, const double *u, int lmax, double *out, int *count)
+{
+    switch (lmax) {
+    case 0: spinor<0>(n, u, out, count); break;
+    case 1: spinor<1>(n, u, out, count); break;
+    case 4: spinor<4>(n, u, out, count); break;
+    case 9: spinor<9>(n, u, out, count); break;
+    default: break;
+    }
+}

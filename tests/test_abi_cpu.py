@@ -95,7 +95,8 @@ def test_grad_f32_and_jac_validation(L):
 
 def test_interface_variants_validation(L):
     fake = ctypes.c_void_p(0x1000)
-    for fn in ("sh_eval_unit", "sh_eval_unit_f32", "sh_eval_complex", "sh_eval_complex_f32"):
+    for fn in ("sh_eval_unit", "sh_eval_unit_f32", "sh_eval_complex", "sh_eval_complex_f32",
+               "sh_eval_spinor", "sh_eval_spinor_f32"):
         assert getattr(L, fn)(10, 5, fake, fake, None) == 1
         assert getattr(L, fn)(3, 5, None, fake, None) == 1
         assert getattr(L, fn)(3, 0, None, None, None) == 0

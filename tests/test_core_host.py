@@ -125,3 +125,30 @@ def test_core_recurrence(core, orc, lmax):
     core.core_rec(u.shape[0], u.ctypes.data, lmax, out.ctypes.data)
     err = np.abs(out.astype(LD) - orc.eval_xyz(lmax, u)).max()
     assert err <= 1e-13, err
+
+
+def test_core_complex(core, orc):
+    core.core_complex9.argtypes = [ctypes.c_long, ctypes.c_void_p, ctypes.c_void_p]
+    u = _units(_pts()[:20000], np.float64)
+    out = np.full((100, u.shape[0], 2), np.nan)
+    core.core_complex9(u.shape[0], u.ctypes.data, out.ctypes.data)
+    re, im = orc.eval_complex_xyz(9, u)
+    assert np.abs(out[..., 0].astype(LD) - re).max() <= 1e-13
+    assert np.abs(out[..., 1].astype(LD) - im).max() <= 1e-13
+
+
+@pytest.mark.parametrize("lmax", [0, 1, 4, 9])
+def test_core_spinor(core, orc, lmax):
+    """Spinor core: every (spinor, component) written exactly once, values equal
+    to the oracle's composition of eq. spinorial."""
+    core.core_spinor.argtypes = [ctypes.c_long, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                 ctypes.c_void_p]
+    u = _units(_pts()[:5000], np.float64)
+    S = 2 * (lmax + 1) ** 2
+    out = np.full((S, 2, u.shape[0], 2), np.nan)
+    count = np.zeros((S, 2, u.shape[0]), dtype=np.int32)
+    core.core_spinor(u.shape[0], u.ctypes.data, lmax, out.ctypes.data, count.ctypes.data)
+    assert (count == 1).all()
+    re, im = orc.eval_spinor_xyz(lmax, u)
+    assert np.abs(out[..., 0].astype(LD) - re).max() <= 1e-13
+    assert np.abs(out[..., 1].astype(LD) - im).max() <= 1e-13

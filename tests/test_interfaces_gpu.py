@@ -1,5 +1,6 @@
-"""GPU parity of the unit-vector and angular input interfaces and of the complex
-harmonics (paper Sections 2-3) against the oracle."""
+"""GPU parity of the unit-vector and angular input interfaces, the complex and
+spinor harmonics and the recurrence beyond l = 9 (paper Sections 2-3,
+Conclusion) against the oracle."""
 from __future__ import annotations
 
 import numpy as np
@@ -68,6 +69,27 @@ def test_complex_harmonics(dev, orc, lmax):
     re32, im32 = orc.eval_complex_xyz(lmax, p32.astype(np.float64))
     assert np.abs(got32.real.astype(LD) - re32).max() <= 5e-6
     assert np.abs(got32.imag.astype(LD) - im32).max() <= 5e-6
+
+
+@pytest.mark.parametrize("lmax", [0, 1, 3, 9])
+def test_spinor_harmonics(dev, orc, lmax):
+    pts = workloads.points_plain_eval(seed=4, n_random=20000)
+    got = sh.sh_eval_spinor(lmax, torch.from_numpy(pts).to(dev)).cpu().numpy()
+    re, im = orc.eval_spinor_xyz(lmax, pts)
+    assert got.shape == re.shape
+    assert np.abs(got.real.astype(LD) - re).max() <= 1e-13
+    assert np.abs(got.imag.astype(LD) - im).max() <= 1e-13
+    p32 = pts.astype(np.float32)
+    got32 = sh.sh_eval_spinor_f32(lmax, torch.from_numpy(p32).to(dev)).cpu().numpy()
+    re32, im32 = orc.eval_spinor_xyz(lmax, p32.astype(np.float64))
+    assert np.abs(got32.real.astype(LD) - re32).max() <= 5e-6
+    assert np.abs(got32.imag.astype(LD) - im32).max() <= 5e-6
+    # the binding's index helper agrees with the oracle's numbering
+    for l in range(lmax + 1):
+        for mj2 in range(-2 * l - 1, 2 * l + 2, 2):
+            assert sh.spinor_index(l, 2 * l + 1, mj2) == orc.spinor_index(l, 1, mj2)
+        for mj2 in range(-2 * l + 1, 2 * l, 2):
+            assert sh.spinor_index(l, 2 * l - 1, mj2) == orc.spinor_index(l, -1, mj2)
 
 
 @pytest.mark.parametrize("lmax", [0, 5, 9, 12, 18, 24])

@@ -347,3 +347,37 @@ def test_high_l_mpmath_addition_and_quadrature(orc):
     Yq = orc.eval_angles(L, th.astype(LD), ph.astype(LD)).astype(np.float64)
     G = (Yq * w) @ Yq.T
     assert np.abs(G - np.eye((L + 1) ** 2)).max() <= 1e-13
+
+
+def test_spinor_harmonics_closed_forms(orc):
+    """Spinor harmonics (eq. spinorial): for every j the sum over m_j of |Omega|^2
+    is (2j+1)/(4 pi) at every direction; they are orthonormal under exact
+    quadrature; l = 0 gives pure spin up/down Y_0^0."""
+    lmax = 4
+    pts = workloads.isotropic_points(300, 0.1, 5, seed=91)
+    re, im = orc.eval_spinor_xyz(lmax, pts)
+    for l in range(lmax + 1):
+        for kappa in (-1, 1):
+            if kappa < 0 and l == 0:
+                continue
+            j2 = 2 * l + kappa
+            ks = [orc.spinor_index(l, kappa, mj2) for mj2 in range(-j2, j2 + 1, 2)]
+            tot = (re[ks] ** 2 + im[ks] ** 2).sum(axis=(0, 1))
+            ref = LD(j2 + 1) / (4 * PI_LD)
+            assert (np.abs(tot - ref) / ref).max() <= 1e-17
+    y00 = 1 / np.sqrt(4 * PI_LD)
+    up, dn = orc.spinor_index(0, 1, 1), orc.spinor_index(0, 1, -1)
+    assert np.abs(re[up, 0] - y00).max() <= 1e-18 and np.all(re[up, 1] == 0)
+    assert np.abs(re[dn, 1] - y00).max() <= 1e-18 and np.all(re[dn, 0] == 0)
+    # orthonormality: Gauss-Legendre in cos(theta) x uniform phi, exact for l <= 4
+    xg, wg = np.polynomial.legendre.leggauss(lmax + 2)
+    nphi = 2 * lmax + 3
+    th = np.repeat(np.arccos(xg), nphi)
+    ph = np.tile(2 * np.pi * np.arange(nphi) / nphi, lmax + 2)
+    w = np.repeat(wg, nphi) * (2 * np.pi / nphi)
+    q = np.stack([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)], axis=1)
+    r2, i2 = orc.eval_spinor_xyz(lmax, q)
+    Z = (r2 + 1j * i2).astype(np.complex128).reshape(r2.shape[0], -1)  # [spinor][2 n]
+    W = np.tile(w, 2)
+    G = (Z.conj() * W) @ Z.T
+    assert np.abs(G - np.eye(r2.shape[0])).max() <= 1e-13
