@@ -62,7 +62,46 @@ def _parse():
     ap.add_argument("--serve-requests", type=int, default=10_000)
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the headline, copy 4 GiB once (calibrates HBM traffic counters)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="no GPU work: turn the counter_collection.csv files of a --pmc FETCH_SIZE and a "
+                         "--pmc WRITE_SIZE run of `--copy-probe` into the committed traffic record")
     return ap.parse_args()
+
+
+HEADLINE_KERNEL = "shk::fwd_kernel<9, double, 2, (shk::In)0>"
+COPY_BYTES = 8 << 29  # the copy probe's 4 GiB
+
+
+def traffic_from_counters(fetch_csv: str, write_csv: str, n_points: int) -> dict:
+    """HBM bytes per launch of the headline kernel from two rocprofv3 counter runs
+    (KiB per dispatch), each scaled so that the copy probe's reading equals the 4 GiB
+    it reads (FETCH_SIZE) and writes (WRITE_SIZE)."""
+    import csv
+
+    def per_dispatch(path, counter):
+        acc = {}
+        with open(path, newline="") as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] != counter:
+                    continue
+                k = (r["Dispatch_Id"], r["Kernel_Name"])
+                acc[k] = acc.get(k, 0.0) + float(r["Counter_Value"])
+        head = [v for (d, name), v in acc.items() if HEADLINE_KERNEL in name]
+        copy = [v for (d, name), v in acc.items() if "copyBuffer" in name and v * 1024 > COPY_BYTES / 4]
+        if not head or len(copy) != 1:
+            raise SystemExit(f"{path}: expected headline dispatches and one copy-probe dispatch")
+        return head, copy[0]
+
+    fh_, fc = per_dispatch(fetch_csv, "FETCH_SIZE")
+    wh, wc = per_dispatch(write_csv, "WRITE_SIZE")
+    fs, ws = COPY_BYTES / (fc * 1024), COPY_BYTES / (wc * 1024)
+    fetch = fs * 1024 * sum(fh_) / len(fh_)
+    write = ws * 1024 * sum(wh) / len(wh)
+    return {"kernel": HEADLINE_KERNEL, "n_points": n_points, "source_sha256": fwd_source_hash(),
+            "fetch_scale": fs, "write_scale": ws, "fetch_bytes_per_launch": fetch,
+            "write_bytes_per_launch": write, "traffic_bytes_per_launch": fetch + write,
+            "algorithmic_bytes_per_launch": n_points * (24 + 800),
+            "dispatches": {"fetch": len(fh_), "write": len(wh)}}
 
 
 def _log(*a):
@@ -119,7 +158,8 @@ def write_probe(buf, steps):
 def bench_interfaces(sh, xyz, out, steps):
     """lmax 9 through the other interfaces on the same points: unit vectors (no
     normalisation), angles (theta, phi), complex output (2^25 points, 16 B
-    per value) and spinor output (2^23 points, 400 complex values each)."""
+    per value), spinor output (2^23 points, 400 complex values each) and the
+    recurrence at lmax 16 (2^24 points)."""
     import torch
     n = xyz.shape[0]
     r = xyz.norm(dim=1, keepdim=True)
@@ -152,6 +192,15 @@ def bench_interfaces(sh, xyz, out, steps):
     b = ns * (24 + 6400)
     res["spinor"] = {"n_points": ns, "points_per_s": ns / avg, "kernel_ms": avg * 1e3, "gbs": b / avg / 1e9,
                      "frac": b / avg / 1e9 / HBM_PEAK_GBS, "bytes_per_point": 6424}
+    # l > 9 by recurrence: lmax 16 (289 rows) on 2^24 points
+    nr = n // 4
+    orr = out.view(-1)[: 289 * nr].view(289, nr)
+    xr = xyz[:nr].contiguous()
+    _, per = time_launches(lambda: sh.sh_eval_rec(16, xr, out=orr), steps, 2)
+    avg = sum(per) / len(per)
+    b = nr * (24 + 289 * 8)
+    res["rec_l16"] = {"n_points": nr, "points_per_s": nr / avg, "kernel_ms": avg * 1e3, "gbs": b / avg / 1e9,
+                      "frac": b / avg / 1e9 / HBM_PEAK_GBS, "bytes_per_point": 24 + 289 * 8}
     return res
 
 
@@ -288,6 +337,13 @@ def cpu_baseline(pts, lmax, sample):
 
 def main():
     args = _parse()
+    if args.traffic_from:
+        t = traffic_from_counters(*args.traffic_from, n_points=args.n)
+        with open(TRAFFIC_FILE, "w") as fh:
+            json.dump(t, fh, indent=1)
+            fh.write("\n")
+        print(json.dumps(t))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the method needs no communication: a multi-GPU run shards the points)",
@@ -338,7 +394,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": head["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": head["frac"], "traffic": measured_traffic(),
                      "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated)",
-                     "kernel": "shk::fwd_kernel<9, double, 2>", "kernel_ms": head["kernel_ms"],
+                     "kernel": HEADLINE_KERNEL, "kernel_ms": head["kernel_ms"],
                      "bytes_per_point": head["bytes_per_point"]},
     }
 
