@@ -264,7 +264,7 @@ def bench_serving(sh, workloads, dev, n_req):
     """n_req projector requests (lmax ~ U{0..9}, n log-uniform in [1e3, 1e6], 80%
     FP64), per-atom points and radial tables resident on the device, 64 GB budget.
     First a closed loop (everything submitted at once) gives the saturation rate;
-    then Poisson arrivals at 0.7x that rate give the latencies."""
+    then Poisson arrivals at 0.7x and 0.3x that rate give the latencies."""
     import numpy as np
     import torch
     from paper_2510_05282_amd.serve import SH_REQ_AUTORELEASE, Server
@@ -309,30 +309,54 @@ def bench_serving(sh, workloads, dev, n_req):
     out["closed_loop"] = {"wall_s": wall, "req_per_s": rate, "points_per_s": total_points / wall,
                           "gbs": total_bytes / wall / 1e9, "batches": st["batches"],
                           "deferred": st["deferred"], "peak_bytes": st["peak_bytes"]}
-    lam = 0.7 * rate
-    arr = workloads.request_stream(n_req=n_req, rate=lam, seed=0)
-    wall, st, lat = run([r.arrival for r in arr])
-    span = st["last_done_s"] - st["first_submit_s"]
-    out["poisson"] = {"rate_req_per_s": lam, "p50_ms": float(np.percentile(lat, 50)),
-                      "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
-                      "points_per_s": total_points / span, "gbs": total_bytes / span / 1e9,
-                      "batches": st["batches"], "deferred": st["deferred"], "peak_bytes": st["peak_bytes"],
-                      "completed": st["completed"], "failed": st["failed"]}
+    for key, frac in (("poisson", 0.7), ("poisson_0.3", 0.3)):
+        lam = frac * rate
+        arr = workloads.request_stream(n_req=n_req, rate=lam, seed=0)
+        wall, st, lat = run([r.arrival for r in arr])
+        span = st["last_done_s"] - st["first_submit_s"]
+        out[key] = {"rate_req_per_s": lam, "p50_ms": float(np.percentile(lat, 50)),
+                    "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
+                    "points_per_s": total_points / span, "gbs": total_bytes / span / 1e9,
+                    "batches": st["batches"], "deferred": st["deferred"], "peak_bytes": st["peak_bytes"],
+                    "completed": st["completed"], "failed": st["failed"]}
     radial.close()
     return out
 
 
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(pts, lmax, sample):
+    """The oracle on the host: all its OpenMP threads on `sample` points, then one
+    thread on a 32x smaller sample (comparable with a single-core figure)."""
     import oracle
     chunk = 1 << 18
     n = min(sample, pts.shape[0])
+    cores = oracle.num_threads()
     t0 = time.perf_counter()
     for c in range(0, n, chunk):
         oracle.eval_xyz(lmax, pts[c:min(n, c + chunk)])
     dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "points/s", "cores": oracle.num_threads(), "kind": "oracle",
+    n1 = max(1, n // 32)
+    oracle.set_num_threads(1)
+    t1 = time.perf_counter()
+    for c in range(0, n1, chunk):
+        oracle.eval_xyz(lmax, pts[c:min(n1, c + chunk)])
+    dt1 = time.perf_counter() - t1
+    oracle.set_num_threads(cores)
+    return {"value": n / dt, "unit": "points/s", "cores": cores, "kind": "oracle",
             "sample": f"first {n} points of the same 2^26-point workload, lmax {lmax}, long double, "
-                      f"{dt:.1f} s"}
+                      f"{dt:.1f} s",
+            "cpu_model": _cpu_model(), "one_thread_value": n1 / dt1,
+            "one_thread_sample": f"first {n1} points, 1 thread, {dt1:.1f} s"}
 
 
 def main():

@@ -65,6 +65,11 @@ def num_threads() -> int:
     return int(lib().orc_num_threads())
 
 
+def set_num_threads(k: int) -> None:
+    """Use k OpenMP threads in later batch calls."""
+    lib().orc_set_num_threads(int(k))
+
+
 def _p(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p)
 
