@@ -217,7 +217,7 @@ int sh_radial_create(int lmax, int n_tables, int n_r, double r_max, const double
     e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipMemcpyAsync(y, host_values, sizeof(double) * nval, hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
-        e = shk::launch_spline_setup(y, table, scratch, int(n_ch), n_r, r_max / double(n_r - 1), st);
+        e = shk::launch_spline_setup(y, table, scratch, int(n_ch), lmax + 1, n_r, r_max / double(n_r - 1), st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     rc = hip_status(e);
 done:
@@ -319,7 +319,7 @@ int sh_server_add_atom(sh_server_t srv, int dtype, int64_t n, const void *points
     for (int q = 0; q < 3; ++q) a.c[q] = center[q];
     if (radial) {
         if (table < 0 || table >= radial->n_tables) return SH_EINVAL;
-        a.tab = radial->table + int64_t(table) * (radial->lmax + 1) * radial->n_r;
+        a.tab = radial->table + int64_t(table) * radial->n_r * (radial->lmax + 1);
         a.tab_lmax = radial->lmax;
         a.n_r = radial->n_r;
         a.h = radial->h;

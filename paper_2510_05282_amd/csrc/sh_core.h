@@ -36,6 +36,18 @@ __host__ __device__ __forceinline__ void static_for(F&& f)
     }
 }
 
+// The hardware deals consecutive workgroups round-robin to the 8 XCDs (each with
+// its own L2).  xcd_tile(b, G) is the logical workgroup of hardware workgroup b
+// in a grid of G: a bijection on [0, G) under which the workgroups each XCD runs
+// form one contiguous range.
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t G)
+{
+    const uint32_t q = G / kXcds, r = G % kXcds, x = b % kXcds;
+    return x * q + (x < r ? x : r) + b / kXcds;
+}
+
 // Scalar type of a (possibly vector) arithmetic type.
 template <typename T> struct scalar_of { using type = T; };
 template <typename S, int N> struct scalar_of<S __attribute__((ext_vector_type(N)))> { using type = S; };

@@ -20,18 +20,9 @@
 namespace shk {
 
 constexpr int kFwdBlock = 256;
-constexpr int kXcds = 8;
 
 template <typename S, int N> struct vec_of { typedef S type __attribute__((ext_vector_type(N))); };
 template <typename S> struct vec_of<S, 1> { typedef S type; };
-
-// Logical workgroup of hardware workgroup b in a grid of G: a bijection on
-// [0, G) that makes the workgroups dispatched to each XCD contiguous.
-__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t G)
-{
-    const uint32_t q = G / kXcds, r = G % kXcds, x = b % kXcds;
-    return x * q + (x < r ? x : r) + b / kXcds;
-}
 
 template <typename V, int PPL>
 __device__ __forceinline__ auto& lane(V& v, int k)

@@ -11,7 +11,7 @@ struct sh_radial {
     int n_r;       // knots per channel (uniform grid on [0, r_max])
     double r_max;
     double h;      // knot spacing r_max / (n_r - 1)
-    double2* table;  // device, [n_tables][lmax+1][n_r] of (y, M)
+    double2* table;  // device, [n_tables][n_r][lmax+1] of (y, M)
 };
 
 namespace shk {
@@ -63,9 +63,10 @@ struct ProjArgs {
 template <typename TIO>
 hipError_t launch_projectors(int lmax, const ProjArgs<TIO>& A, hipStream_t s);
 
-// Natural-spline second derivatives for n_ch channels of n_r values y (device):
-// writes (y, M) pairs to table; scratch holds n_ch * n_r doubles.
-hipError_t launch_spline_setup(const double* y, double2* table, double* scratch, int n_ch, int n_r, double h,
-                               hipStream_t s);
+// Natural-spline second derivatives for n_ch = n_tables * ch channels of n_r
+// values y[n_ch][n_r] (device): writes (y, M) pairs to table[n_tables][n_r][ch];
+// scratch holds n_ch * n_r doubles.
+hipError_t launch_spline_setup(const double* y, double2* table, double* scratch, int n_ch, int ch, int n_r,
+                               double h, hipStream_t s);
 
 }  // namespace shk

@@ -1,5 +1,10 @@
 // sh_proj.h -- per-point projector evaluation shared by the projector and
 // serving kernels: spline lookup of R_l(r) and the product R_l(r) * R_l^m(d).
+//
+// Radial table layout (one table): [n_r][ch] of (y_i, M_i) -- knot i of every
+// channel is adjacent, so the interval [i, i+1] of all channels of a point is
+// 2 ch consecutive double2 (one 128-byte line for ch = 4) instead of ch lines
+// n_r * 16 bytes apart.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -14,20 +19,53 @@ struct SplineGrid {
     double h, inv_h, r_max, h2_over_6;
 };
 
-// Spline value at r >= 0: interval i = floor(r/h) clamped to [0, n_r-2],
-// t = r/h - i, A = 1 - t, B = t,
+// R_0 .. R_{NL-1} at r >= 0 from a table with ch >= NL channels: interval
+// i = floor(r/h) clamped to [0, n_r-2], t = r/h - i, A = 1 - t, B = t,
 //     S = A y_i + B y_{i+1} + ((A^3 - A) M_i + (B^3 - B) M_{i+1}) h^2/6;
-// 0 beyond r_max.
-__device__ __forceinline__ double spline_eval(const double2* __restrict__ tab, const SplineGrid& g, double r)
+// 0 beyond r_max; a NaN r gives NaN.
+template <int NL, typename TIO>
+__host__ __device__ __forceinline__ void spline_eval(const double2* __restrict__ tab, int ch, const SplineGrid& g, double r,
+                                            TIO (&R)[NL])
 {
-    if (!(r <= g.r_max)) return r != r ? r : 0.0;  // NaN stays NaN
+    if (!(r <= g.r_max)) {
+        const double v = r != r ? r : 0.0;
+        static_for<0, NL>([&](auto lc) { R[decltype(lc)::value] = TIO(v); });
+        return;
+    }
     const double q = r * g.inv_h;
     int i = int(q);
     i = i > g.n_r - 2 ? g.n_r - 2 : i;
     const double t = q - double(i);
-    const double2 a = tab[i], b = tab[i + 1];
     const double A = 1.0 - t, B = t;
-    return A * a.x + B * b.x + ((A * A * A - A) * a.y + (B * B * B - B) * b.y) * g.h2_over_6;
+    const double2* k0 = tab + int64_t(i) * ch;
+    const double2* k1 = k0 + ch;
+    static_for<0, NL>([&](auto lc) {
+        constexpr int L = decltype(lc)::value;
+        const double2 a = k0[L], b = k1[L];
+        R[L] = TIO(A * a.x + B * b.x + ((A * A * A - A) * a.y + (B * B * B - B) * b.y) * g.h2_over_6);
+    });
+}
+
+// Natural cubic spline on a uniform grid for one channel.  With knot spacing h
+// the second derivatives solve, for k = 1 .. n_r-2,
+//     M_{k-1} + 4 M_k + M_{k+1} = 6 (y_{k+1} - 2 y_k + y_{k-1}) / h^2,
+// M_0 = M_{n_r-1} = 0, by forward elimination and back substitution (cc holds
+// the eliminated super-diagonal).  Knot k's pair (y_k, M_k) goes to
+// tc[k * stride], so the channels of a table can be interleaved.
+__host__ __device__ inline void spline_solve(const double* __restrict__ yc, double2* __restrict__ tc, int64_t stride,
+                                             double* __restrict__ cc, int n_r, double six_over_h2)
+{
+    for (int k = 0; k < n_r; ++k) tc[k * stride] = make_double2(yc[k], 0.0);
+    double cprev = 0.0, dprev = 0.0;  // forward elimination over k = 1 .. n_r-2 (dp kept in .y)
+    for (int k = 1; k <= n_r - 2; ++k) {
+        const double rhs = six_over_h2 * (yc[k + 1] - 2.0 * yc[k] + yc[k - 1]);
+        const double den = 4.0 - cprev;
+        cprev = 1.0 / den;
+        dprev = (rhs - dprev) / den;
+        cc[k] = cprev;
+        tc[k * stride].y = dprev;
+    }
+    for (int k = n_r - 3; k >= 1; --k) tc[k * stride].y -= cc[k] * tc[(k + 1) * stride].y;  // M_{n_r-1} = 0
 }
 
 __host__ __device__ constexpr int l_of_row(int r)
@@ -37,25 +75,55 @@ __host__ __device__ constexpr int l_of_row(int r)
     return l;
 }
 
-// All projector values of one point: d = p - c, R_l(|d|) from `tab` (channel l
-// at tab + l * n_r), harmonics of d; value of row f goes to out[f * stride].
+// All projector values of one point p (coordinates already loaded): d = p - c,
+// R_l(|d|) from the table `tab` with `ch` channels, harmonics of d; the value of
+// row f goes to out[f * stride].
 template <int LMAX, typename TIO>
-__device__ __forceinline__ void proj_point(const TIO* __restrict__ p, const double c[3],
-                                           const double2* __restrict__ tab, const SplineGrid& g,
+__device__ __forceinline__ void proj_point(double px, double py, double pz, const double c[3],
+                                           const double2* __restrict__ tab, int ch, const SplineGrid& g,
                                            TIO* __restrict__ out, int64_t stride)
 {
-    const double dx = double(p[0]) - c[0], dy = double(p[1]) - c[1], dz = double(p[2]) - c[2];
+    const double dx = px - c[0], dy = py - c[1], dz = pz - c[2];
     double xb, yb, zb, keep;
     normalize(dx, dy, dz, xb, yb, zb, keep);
     const double r = sqrt(__builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz)));
     TIO R[LMAX + 1];
-    static_for<0, LMAX + 1>([&](auto lc) {
-        constexpr int L = decltype(lc)::value;
-        R[L] = TIO(spline_eval(tab + int64_t(L) * g.n_r, g, r));
-    });
-    eval_unit<LMAX, TIO>(TIO(xb), TIO(yb), TIO(zb), TIO(keep), [&](int f, TIO v) {
-        __builtin_nontemporal_store(R[l_of_row(f)] * v, out + int64_t(f) * stride);
-    });
+    spline_eval<LMAX + 1, TIO>(tab, ch, g, r, R);
+    eval_unit<LMAX, TIO>(TIO(xb), TIO(yb), TIO(zb), TIO(keep),
+                         [&](int f, TIO v) { out[int64_t(f) * stride] = R[l_of_row(f)] * v; });
+}
+
+// Wave-wide search over n sorted keys: the last k in [0, n) with keys[k] <= x,
+// or -1 if there is none.  Every lane must be active and pass the same x; each
+// round the 64 lanes probe 64 evenly spaced keys and a ballot keeps the bracket,
+// so n keys take ceil(log64 n) dependent loads.  Keys that are not sorted still
+// give some k in [0, n) (callers check what they use).
+__device__ __forceinline__ int wave_search(const int64_t* __restrict__ keys, int n, int64_t x)
+{
+    const int lane = threadIdx.x & 63;
+    int lo = 0, hi = n;  // the answer lies in [lo, hi)
+    while (hi - lo > 1) {
+        const int step = (hi - lo + 63) / 64;
+        const int k = lo + lane * step;
+        const bool pred = k < hi && keys[k] <= x;
+        const int c = __popcll(__ballot(pred));  // lanes 0 .. c-1 probe keys <= x
+        if (c == 0) return -1;
+        lo += (c - 1) * step;
+        hi = min(lo + step, hi);
+    }
+    return keys[lo] <= x ? lo : -1;
+}
+
+// The same for one lane (binary search): the last k in [0, n) with keys[k] <= x, or 0.
+__device__ __forceinline__ int lane_search(const int64_t* __restrict__ keys, int n, int64_t x)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (keys[mid] <= x) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
 }
 
 }  // namespace shk

@@ -2,9 +2,9 @@
 // batch on one of n_slots streams.
 //
 // A batch is a list of requests of any lmax and either dtype.  Each request is cut
-// into 256-point tiles; block b handles tile b of the batch, finds its request by
-// a wave-parallel search over the requests' first-tile indices (64 lanes probe 64
-// evenly spaced entries per round, a ballot keeps the bracket), and runs the same
+// into 256-point tiles; block b handles tile xcd_tile(b) of the batch (so each XCD
+// works through a contiguous run of requests and their tables), finds its request by
+// a wave-wide search over the requests' first-tile indices, and runs the same
 // per-point projector evaluation as sh_projectors, dispatching once per block on
 // the request's (dtype, lmax).  Request descriptors travel host -> device through
 // a pinned staging buffer per slot (the slot is reused only after its previous
@@ -29,16 +29,17 @@ struct ServeDesc {
     int64_t n;
     int64_t tile0;  // first tile of this request within the batch
     int n_r;
+    int ch;  // channels of the table (its lmax + 1)
     int lmax;
     int dtype;
-    int pad;
 };
 
 template <int LMAX, typename TIO>
 __device__ __forceinline__ void serve_point(const ServeDesc& d, int64_t j)
 {
     const SplineGrid g{d.n_r, d.h, d.inv_h, d.r_max, d.h2_over_6};
-    proj_point<LMAX, TIO>(static_cast<const TIO*>(d.points) + 3 * j, d.c, d.tab, g,
+    const TIO* p = static_cast<const TIO*>(d.points) + 3 * j;
+    proj_point<LMAX, TIO>(double(p[0]), double(p[1]), double(p[2]), d.c, d.tab, d.ch, g,
                           static_cast<TIO*>(d.out) + j, d.n);
 }
 
@@ -60,28 +61,12 @@ __device__ __forceinline__ void serve_dispatch(const ServeDesc& d, int64_t j)
     }
 }
 
-// Last k in [0, n) with tile0[k] <= tile (tile0 increasing, tile0[0] = 0 <= tile).
-// Every lane of the wave returns the same k.
-__device__ __forceinline__ int find_item(const int64_t* __restrict__ tile0, int n, int64_t tile)
-{
-    const int lane = threadIdx.x & 63;
-    int lo = 0, hi = n;  // the answer lies in [lo, hi)
-    while (hi - lo > 1) {
-        const int step = (hi - lo + 63) / 64;
-        const int k = lo + lane * step;
-        const bool pred = k < hi && tile0[k] <= tile;
-        const int c = __popcll(__ballot(pred));  // lanes 0 .. c-1 hold entries <= tile
-        lo += (c - 1) * step;
-        hi = min(lo + step, hi);
-    }
-    return lo;
-}
-
 __global__ __launch_bounds__(256) void serve_kernel(const ServeDesc* __restrict__ descs,
                                                     const int64_t* __restrict__ tile0, int n_items)
 {
-    const int64_t tile = blockIdx.x;
-    const ServeDesc& d = descs[find_item(tile0, n_items, tile)];
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    // tile0 is increasing with tile0[0] = 0 <= tile, so the search finds an item
+    const ServeDesc& d = descs[wave_search(tile0, n_items, tile)];
     const int64_t j = (tile - d.tile0) * 256 + threadIdx.x;
     if (j < 0 || j >= d.n) return;
     if (d.dtype == SH_F64) serve_dispatch<double>(d, j);
@@ -153,6 +138,7 @@ public:
             d.tile0 = tiles;
             tile0[k] = tiles;
             d.n_r = it.atom.n_r;
+            d.ch = it.atom.tab_lmax + 1;
             d.lmax = it.lmax;
             d.dtype = it.atom.dtype;
             tiles += (it.atom.n + 255) / 256;

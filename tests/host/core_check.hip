@@ -1,6 +1,9 @@
 // Test-only: host build of the GPU formula core (sh_core.h), so the factorised
 // formulas and their constants can be checked on the CPU against the oracle.
 // Inputs are unit vectors; the kernels' FP64 normalisation is not part of this.
+// Also the radial spline (sh_proj.h) in the device table layout.
+#include <vector>
+
 #include "../../paper_2510_05282_amd/csrc/sh_core.h"
 
 template <int LMAX, typename T>
@@ -109,5 +112,28 @@ extern "C" void core_spinor(long n, const double *u, int lmax, double *out, int 
     case 4: spinor<4>(n, u, out, count); break;
     case 9: spinor<9>(n, u, out, count); break;
     default: break;
+    }
+}
+
+#include "../../paper_2510_05282_amd/csrc/sh_proj.h"
+
+// Radial tables in the device layout: y[n_tables][4][n_r] -> interleaved
+// [n_tables][n_r][4] (y, M) by spline_solve, then R_0..R_3 of table t at r[k]:
+// out[k][4].
+extern "C" void core_spline4(int n_tables, int n_r, double r_max, const double *y, int t, long n, const double *r,
+                             double *out)
+{
+    const int ch = 4;
+    const double h = r_max / double(n_r - 1);
+    std::vector<double2> tab(size_t(n_tables) * n_r * ch);
+    std::vector<double> cc(n_r);
+    for (int c = 0; c < n_tables * ch; ++c)
+        shk::spline_solve(y + long(c) * n_r, tab.data() + long(c / ch) * n_r * ch + c % ch, ch, cc.data(), n_r,
+                          6.0 / (h * h));
+    const shk::SplineGrid g{n_r, h, 1.0 / h, r_max, h * h / 6.0};
+    for (long k = 0; k < n; ++k) {
+        double R[4];
+        shk::spline_eval<4, double>(tab.data() + long(t) * n_r * ch, ch, g, r[k], R);
+        for (int l = 0; l < 4; ++l) out[4 * k + l] = R[l];
     }
 }

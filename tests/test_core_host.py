@@ -152,3 +152,23 @@ def test_core_spinor(core, orc, lmax):
     re, im = orc.eval_spinor_xyz(lmax, u)
     assert np.abs(out[..., 0].astype(LD) - re).max() <= 1e-13
     assert np.abs(out[..., 1].astype(LD) - im).max() <= 1e-13
+
+
+def test_core_spline_interleaved_tables(core, orc):
+    """The device spline (solve and lookup in the channel-interleaved table layout)
+    against the oracle's natural spline, every channel of several tables."""
+    core.core_spline4.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_int,
+                                  ctypes.c_long, ctypes.c_void_p, ctypes.c_void_p]
+    rng = np.random.default_rng(12)
+    n_tables, n_r, r_max = 3, 257, 3.0
+    y = np.stack([workloads.radial_table(rng, 3, n_r, r_max) for _ in range(n_tables)])
+    y = np.ascontiguousarray(y)
+    knots = np.linspace(0.0, r_max, n_r)
+    r = np.concatenate([rng.uniform(0, r_max, 4000), knots, [r_max, r_max * (1 + 1e-12), 4.0, 0.0]])
+    for t in range(n_tables):
+        out = np.empty((r.shape[0], 4))
+        core.core_spline4(n_tables, n_r, r_max, y.ctypes.data, t, r.shape[0], r.ctypes.data, out.ctypes.data)
+        for l in range(4):
+            M = orc.spline_setup(y[t, l], r_max)
+            ref = orc.spline_eval(y[t, l], M, r_max, r)
+            assert np.abs(out[:, l].astype(LD) - ref).max() <= 1e-13, (t, l)
