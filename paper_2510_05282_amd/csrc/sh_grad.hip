@@ -15,6 +15,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "sh_core.h"
 #include "sh_dual.h"
 #include "sh_internal.h"
@@ -91,39 +93,68 @@ template hipError_t launch_grad<float>(int, int64_t, const float*, const float*,
 
 // Values out[F][ld] and the Jacobian jac[3][F][ld] (d R_f / d x_k at
 // jac[(k F + f) ld + i]) in one pass: the dual-number core gives P and grad_u P,
-// which is projected with (1/r)(I - u u^T).
-template <int LMAX>
+// which is projected with (1/r)(I - u u^T).  The launch follows the forward
+// kernel's (4F + 3 doubles per point, all but 3 of them row stores): PPL = 2
+// adjacent points per lane with 16-byte row stores, workgroups in XCD-contiguous
+// order, at most 2 resident workgroups per CU; PPL = 1 for odd ld or a
+// remainder point.
+constexpr size_t kJacCapLds = 54 * 1024;
+
+template <int LMAX, int PPL>
 __global__ __launch_bounds__(kGradBlock) void jac_kernel(const double* __restrict__ xyz, double* __restrict__ out,
                                                          double* __restrict__ jac, uint32_t n, int64_t ld)
 {
     constexpr int F = nfun(LMAX);
-    const uint32_t i = blockIdx.x * kGradBlock + threadIdx.x;
-    if (i >= n) return;
-    const double* p = xyz + 3 * size_t(i);
-    double xb, yb, zb, keep, rinv;
-    normalize(p[0], p[1], p[2], xb, yb, zb, keep, rinv);
-    const uint32_t boff = i * uint32_t(sizeof(double));
+    using V = std::conditional_t<PPL == 1, double, double2_t>;
+    const uint32_t i0 = (xcd_tile(blockIdx.x, gridDim.x) * kGradBlock + threadIdx.x) * PPL;
+    if (i0 >= n) return;
+    V x, y, z, k, ri;
+#pragma unroll
+    for (int q = 0; q < PPL; ++q) {
+        const double* p = xyz + 3 * size_t(i0 + q);
+        double xb, yb, zb, kb, rb;
+        normalize(p[0], p[1], p[2], xb, yb, zb, kb, rb);
+        if constexpr (PPL == 1) {
+            x = xb, y = yb, z = zb, k = kb, ri = rb;
+        } else {
+            x[q] = xb, y[q] = yb, z[q] = zb, k[q] = kb, ri[q] = rb;
+        }
+    }
+    const uint32_t boff = i0 * uint32_t(sizeof(double));
     auto at = [&](double* base, int64_t r) {
-        return reinterpret_cast<double*>(reinterpret_cast<char*>(base + r * ld) + boff);
+        return reinterpret_cast<V*>(reinterpret_cast<char*>(base + r * ld) + boff);
     };
-    eval_unit_jac<LMAX, double>(xb, yb, zb, keep, [&](int f, double v, double gx, double gy, double gz) {
-        const double ug = xb * gx + yb * gy + zb * gz;
+    eval_unit_jac<LMAX, V>(x, y, z, k, [&](int f, V v, V gx, V gy, V gz) {
+        const V ug = x * gx + y * gy + z * gz;
         *at(out, f) = v;
-        *at(jac, f) = rinv * (gx - xb * ug);
-        *at(jac, F + f) = rinv * (gy - yb * ug);
-        *at(jac, 2 * F + f) = rinv * (gz - zb * ug);
+        *at(jac, f) = ri * (gx - x * ug);
+        *at(jac, F + f) = ri * (gy - y * ug);
+        *at(jac, 2 * F + f) = ri * (gz - z * ug);
     });
+}
+
+template <int LMAX, int PPL>
+static hipError_t launch_jac_one(int64_t n, const double* xyz, double* out, double* jac, int64_t ld, hipStream_t s)
+{
+    const unsigned grid = unsigned((n / PPL + kGradBlock - 1) / kGradBlock);
+    hipLaunchKernelGGL((jac_kernel<LMAX, PPL>), dim3(grid), dim3(kGradBlock), PPL > 1 ? kJacCapLds : 0, s, xyz, out,
+                       jac, uint32_t(n), ld);
+    return hipGetLastError();
 }
 
 template <int LMAX>
 static hipError_t launch_jac_l(int64_t n, const double* xyz, double* out, double* jac, int64_t ld, hipStream_t s)
 {
+    const bool vec_ok = ld % 2 == 0 && reinterpret_cast<uintptr_t>(out) % 16 == 0 &&
+                        reinterpret_cast<uintptr_t>(jac) % 16 == 0;
     for (int64_t c0 = 0; c0 < n; c0 += kGradChunk) {
         const int64_t nc = n - c0 < kGradChunk ? n - c0 : kGradChunk;
-        const unsigned grid = unsigned((nc + kGradBlock - 1) / kGradBlock);
-        hipLaunchKernelGGL((jac_kernel<LMAX>), dim3(grid), dim3(kGradBlock), 0, s, xyz + 3 * c0, out + c0,
-                           jac + c0, uint32_t(nc), ld);
-        hipError_t e = hipGetLastError();
+        const int64_t nmain = vec_ok ? nc - nc % 2 : 0;
+        hipError_t e = hipSuccess;
+        if (nmain) e = launch_jac_one<LMAX, 2>(nmain, xyz + 3 * c0, out + c0, jac + c0, ld, s);
+        if (e == hipSuccess && nmain < nc)
+            e = launch_jac_one<LMAX, 1>(nc - nmain, xyz + 3 * (c0 + nmain), out + c0 + nmain, jac + c0 + nmain, ld,
+                                        s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

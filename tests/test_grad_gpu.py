@@ -142,9 +142,13 @@ def test_grad_fp32_parity(dev, orc):
         assert err <= 2e-5
 
 
-def test_fused_values_and_jacobian(dev, orc):
+@pytest.mark.parametrize("extra", [0, 1])
+def test_fused_values_and_jacobian(dev, orc, extra):
+    """5003 points (odd: one point per lane) and 5004 (two points per lane)."""
     pts = np.concatenate([workloads.points_gradient(n=5000, seed=40),
-                          np.array([[0, 0, 1.5], [0, 0, 0.0], [2.0, 0, 0]])])
+                          np.array([[0, 0, 1.5], [0, 0, 0.0], [2.0, 0, 0]]),
+                          np.array([[0.3, -0.2, 0.1]])[:extra]])
+    origin = int(np.flatnonzero(np.all(pts == 0, axis=1))[0])
     for lmax in (0, 3, 9):
         F = (lmax + 1) ** 2
         y, j = sh.sh_eval_jac(lmax, torch.from_numpy(pts).to(dev))
@@ -153,7 +157,7 @@ def test_fused_values_and_jacobian(dev, orc):
         J = orc.jacobian_xyz(lmax, pts)
         scale = 1 + np.abs(J.astype(np.float64)).max()
         assert np.abs(j.astype(LD) - J).max() <= 1e-12 * scale
-        assert np.all(j[:, :, -2] == 0)  # origin
+        assert np.all(j[:, :, origin] == 0)
         assert y.shape == (F, pts.shape[0])
 
 
