@@ -2,8 +2,7 @@
 // batch on one of n_slots streams.
 //
 // A batch is a list of requests of any lmax and either dtype.  Each request is cut
-// into 256-point tiles; block b handles tile xcd_tile(b) of the batch (so each XCD
-// works through a contiguous run of requests and their tables), finds its request by
+// into 256-point tiles; block b handles tile b of the batch, finds its request by
 // a wave-wide search over the requests' first-tile indices, and runs the same
 // per-point projector evaluation as sh_projectors, dispatching once per block on
 // the request's (dtype, lmax).  Request descriptors travel host -> device through
@@ -64,7 +63,10 @@ __device__ __forceinline__ void serve_dispatch(const ServeDesc& d, int64_t j)
 __global__ __launch_bounds__(256) void serve_kernel(const ServeDesc* __restrict__ descs,
                                                     const int64_t* __restrict__ tile0, int n_items)
 {
-    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    // Tiles are dealt round-robin to the XCDs (no XCD-contiguous remap): the cost of
+    // a tile varies ~100x with its request's lmax, and interleaving keeps the XCDs'
+    // shares of a mixed batch even.
+    const int64_t tile = blockIdx.x;
     // tile0 is increasing with tile0[0] = 0 <= tile, so the search finds an item
     const ServeDesc& d = descs[wave_search(tile0, n_items, tile)];
     const int64_t j = (tile - d.tile0) * 256 + threadIdx.x;
