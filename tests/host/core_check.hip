@@ -73,7 +73,7 @@ extern "C" void core_jac9(long n, const double *u, double *val, double *jac)
 extern "C" void core_rec(long n, const double *u, int lmax, double *out)
 {
     for (long i = 0; i < n; ++i)
-        shk::eval_unit_rec(u[3 * i], u[3 * i + 1], u[3 * i + 2], 1.0, lmax,
+        shk::eval_unit_rec<double>(u[3 * i], u[3 * i + 1], u[3 * i + 2], 1.0, lmax,
                            [&](int r, double v) { out[r * n + i] = v; });
 }
 

@@ -93,8 +93,10 @@ def test_spinor_harmonics(dev, orc, lmax):
 
 
 @pytest.mark.parametrize("lmax", [0, 5, 9, 12, 18, 24])
-def test_recurrence_beyond_l9(dev, orc, lmax):
-    pts = workloads.points_plain_eval(seed=3, n_random=20000)
+@pytest.mark.parametrize("n_random", [20000, 19999])
+def test_recurrence_beyond_l9(dev, orc, lmax, n_random):
+    """Even point counts run two points per lane, odd ones end with a one-point launch."""
+    pts = workloads.points_plain_eval(seed=3, n_random=n_random)
     got = sh.sh_eval_rec(lmax, torch.from_numpy(pts).to(dev)).cpu().numpy()
     assert np.abs(got.astype(LD) - orc.eval_xyz(lmax, pts)).max() <= 1e-13
     if lmax <= 9:  # agrees with the explicit formulas
