@@ -224,7 +224,9 @@ int sh_server_destroy(sh_server_t srv);
 
 /* Registers an atom: n points [n][3] of dtype (device, owned by the caller and
  * kept valid while the server may use them), centre (host, 3 doubles), table
- * `table` of `radial` (NULL only for simulated servers). */
+ * `table` of `radial` (NULL only for simulated servers).  SH_EINVAL if n is not
+ * positive or exceeds 256 * (2^24 - 1) (a batch is one dispatch, whose grid of
+ * 256-point tiles must stay below 2^32 work-items). */
 int sh_server_add_atom(sh_server_t srv, int dtype, int64_t n, const void *points, const double *center,
                        sh_radial_t radial, int table, int *atom_id);
 

@@ -49,10 +49,11 @@ __global__ __launch_bounds__(256) void proj_kernel(const TIO* __restrict__ cente
                                                    const TIO* __restrict__ points, int64_t n_points,
                                                    const double2* __restrict__ table, int tab_ch,
                                                    int n_tables, const int32_t* __restrict__ table_of_atom,
-                                                   SplineGrid g, TIO* __restrict__ out)
+                                                   SplineGrid g, TIO* __restrict__ out, int64_t j0)
 {
     constexpr int F = nfun(LMAX);
-    const int64_t w0 = int64_t(xcd_tile(blockIdx.x, gridDim.x)) * 256 + (threadIdx.x & ~63u);  // wave's first point
+    // first point of this wave; the launch covers points j0 .. j0 + 256 gridDim.x - 1
+    const int64_t w0 = j0 + int64_t(xcd_tile(blockIdx.x, gridDim.x)) * 256 + (threadIdx.x & ~63u);
     if (w0 >= n_points) return;
     const int64_t j = w0 + (threadIdx.x & 63);
     const bool live = j < n_points;
@@ -71,15 +72,22 @@ __global__ __launch_bounds__(256) void proj_kernel(const TIO* __restrict__ cente
                           out + F * o0 + (j - o0), o1 - o0);
 }
 
+// Points per launch: keeps each grid well inside the 32-bit work-item count of a dispatch.
+constexpr int64_t kProjChunk = int64_t(1) << 28;
+
 template <int LMAX, typename TIO>
 static hipError_t launch_proj_l(const ProjArgs<TIO>& A, hipStream_t s)
 {
-    const int64_t grid = (A.n_points + 255) / 256;
-    if (grid > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((proj_kernel<LMAX, TIO>), dim3(unsigned(grid)), dim3(256), 0, s, A.centers, A.offsets,
-                       A.n_atoms, A.points, A.n_points, A.table, A.tab_ch, A.n_tables, A.table_of_atom,
-                       SplineGrid{A.n_r, A.h, 1.0 / A.h, A.r_max, A.h * A.h / 6.0}, A.out);
-    return hipGetLastError();
+    const SplineGrid g{A.n_r, A.h, 1.0 / A.h, A.r_max, A.h * A.h / 6.0};
+    for (int64_t j0 = 0; j0 < A.n_points; j0 += kProjChunk) {
+        const int64_t nc = A.n_points - j0 < kProjChunk ? A.n_points - j0 : kProjChunk;
+        hipLaunchKernelGGL((proj_kernel<LMAX, TIO>), dim3(unsigned((nc + 255) / 256)), dim3(256), 0, s, A.centers,
+                           A.offsets, A.n_atoms, A.points, A.n_points, A.table, A.tab_ch, A.n_tables,
+                           A.table_of_atom, g, A.out, j0);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 template <typename TIO>

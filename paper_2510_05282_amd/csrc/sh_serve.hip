@@ -116,7 +116,8 @@ public:
     }
     int n_slots() const override { return int(slots_.size()); }
     int64_t max_items() const override { return kMaxItems; }
-    int64_t max_tiles() const override { return int64_t(1) << 30; }
+    // a dispatch counts its work-items in 32 bits: tiles * 256 < 2^32
+    int64_t max_tiles() const override { return (int64_t(1) << 24) - 1; }
     void* arena_base() override { return arena_; }
 
     int launch(int slot, const std::vector<Item>& items) override
@@ -146,7 +147,7 @@ public:
             tiles += (it.atom.n + 255) / 256;
         }
         if (items.empty()) return SH_OK;
-        if (tiles > 0x7fffffff) return SH_EINVAL;
+        if (tiles > max_tiles()) return SH_EINVAL;
         // descriptors, then the first-tile index array at a fixed offset
         hipError_t e = hipMemcpyAsync(s.dev, s.host, sizeof(shk::ServeDesc) * items.size(),
                                       hipMemcpyHostToDevice, s.stream);

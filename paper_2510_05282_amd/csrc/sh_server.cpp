@@ -88,6 +88,7 @@ Server::~Server()
 int Server::add_atom(const Atom& a, int* id)
 {
     if (!id || a.n <= 0 || !a.points || (a.dtype != SH_F64 && a.dtype != SH_F32)) return SH_EINVAL;
+    if ((a.n + 255) / 256 > ex_->max_tiles()) return SH_EINVAL;  // one batch could never hold it
     std::lock_guard<std::mutex> g(mu_);
     atoms_.push_back(a);
     *id = int(atoms_.size() - 1);

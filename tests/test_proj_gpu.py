@@ -103,3 +103,45 @@ def test_shared_tables_and_empty_atoms(dev, orc):
 def test_projectors_deterministic(dev):
     A = workloads.atom_spheres(seed=5, n_atoms=8)
     assert np.array_equal(_run(dev, 3, A), _run(dev, 3, A))
+
+
+def test_projectors_across_launch_chunks(dev, orc):
+    """More than 2^28 points: the build runs in several launches.  Two atoms, lmax 1
+    (F = 4), points drawn on the device; sampled points around the chunk boundary
+    and elsewhere are checked against the oracle one by one."""
+    n0, n1 = (1 << 27) + 5, (1 << 27) + 1003
+    n = n0 + n1
+    assert n > (1 << 28)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(3)
+    centers = torch.tensor([[1.0, 2.0, 3.0], [10.0, 9.0, 8.0]], dtype=torch.float64, device=dev)
+    pts = 2.5 * (2 * torch.rand((n, 3), generator=gen, dtype=torch.float64, device=dev) - 1)
+    pts[:n0] += centers[0]
+    pts[n0:] += centers[1]
+    offsets = torch.tensor([0, n0, n], dtype=torch.int64, device=dev)
+    A = workloads.atom_spheres(seed=6, n_atoms=2, radius=1.0, h=0.5, lmax=1, n_r=400)
+    tables = A.tables.copy()
+    r_max = 3.0 * np.sqrt(3.0)  # covers the whole cube around each centre
+    rad = sh.Radial(tables, r_max)
+    out = sh.sh_projectors(1, centers, offsets, pts, rad)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(4)
+    idx = np.unique(np.concatenate([rng.integers(0, n, 3000), np.arange((1 << 28) - 40, (1 << 28) + 40),
+                                    [0, n0 - 1, n0, n - 1]]))
+    idx_t = torch.from_numpy(idx).to(dev)
+    p_s = pts[idx_t].cpu().numpy()
+    atom = (idx >= n0).astype(np.int64)
+    o0 = np.where(atom == 0, 0, n0)
+    na = np.where(atom == 0, n0, n1)
+    F = 4
+    got = np.stack([out[torch.from_numpy(F * o0 + f * na + (idx - o0)).to(dev)].cpu().numpy() for f in range(F)])
+    order = np.argsort(atom, kind="stable")
+    sub_off = np.array([0, int((atom == 0).sum()), idx.shape[0]])
+    ref_flat = orc.projectors(1, centers.cpu().numpy(), sub_off, p_s[order], tables, r_max)
+    ref = np.empty((F, idx.shape[0]), dtype=LD)
+    for a in range(2):
+        sel = order[sub_off[a]:sub_off[a + 1]]
+        m = sub_off[a + 1] - sub_off[a]
+        ref[:, sel] = ref_flat[F * sub_off[a]: F * sub_off[a] + F * m].reshape(F, m)
+    rad.close()
+    assert np.abs(got.astype(LD) - ref).max() <= 1e-13

@@ -147,3 +147,14 @@ def test_drain_waits_for_batches_being_launched():
         st = s.stats()
         assert st["completed"] == 60, st
         s.close()
+
+
+def test_atom_larger_than_one_batch_is_refused():
+    """A batch is one dispatch: an atom whose tiles could not fit one batch grid is
+    refused at registration (the simulated executor allows 2^22 tiles per batch)."""
+    s = _server(1 << 30)
+    limit = 256 * (1 << 22)
+    assert s.add_atom(FAKE, [0, 0, 0], dtype=SH_F32, n=limit) >= 0
+    with pytest.raises(_lib.ShError):
+        s.add_atom(FAKE, [0, 0, 0], dtype=SH_F32, n=limit + 1)
+    s.close()
