@@ -381,3 +381,34 @@ def test_spinor_harmonics_closed_forms(orc):
     W = np.tile(w, 2)
     G = (Z.conj() * W) @ Z.T
     assert np.abs(G - np.eye(r2.shape[0])).max() <= 1e-13
+
+
+def test_library_routine_std_sph_legendre(orc, tmp_path):
+    """libstdc++'s std::sph_legendre(l, m, theta) = Y_l^m(theta, 0), Condon-Shortley
+    phase included, so R_l^0 = Y_l^0 and R_l^{+-m} = sqrt(2) (-1)^m Y_l^m(theta, 0)
+    {cos, sin}(m phi) (eq. real_harmomics)."""
+    import ctypes
+    import shutil
+    import subprocess
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    so = str(tmp_path / "std_sph_legendre.so")
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "host", "std_sph_legendre.cpp")
+    subprocess.check_call([gxx, "-O2", "-std=c++17", "-fPIC", "-shared", src, "-o", so])
+    L = ctypes.CDLL(so)
+    L.std_sph_legendre.argtypes = [ctypes.c_int, ctypes.c_long, ctypes.c_void_p, ctypes.c_void_p]
+    th = np.concatenate([np.arccos(np.random.default_rng(53).uniform(-1, 1, 2000)), [0.0, np.pi, np.pi / 2]])
+    ph = np.random.default_rng(54).uniform(-np.pi, np.pi, th.shape[0])
+    leg = np.empty((55, th.shape[0]))
+    L.std_sph_legendre(9, th.shape[0], th.ctypes.data, leg.ctypes.data)
+    got = orc.eval_angles(9, th.astype(LD), ph.astype(LD)).astype(np.float64)
+    for l in range(10):
+        for m in range(0, l + 1):
+            y = leg[l * (l + 1) // 2 + m]
+            if m == 0:
+                assert np.abs(got[_row(l, 0)] - y).max() <= 1e-14
+            else:
+                s = math.sqrt(2.0) * (-1) ** m
+                assert np.abs(got[_row(l, m)] - s * y * np.cos(m * ph)).max() <= 1e-14
+                assert np.abs(got[_row(l, -m)] - s * y * np.sin(m * ph)).max() <= 1e-14
