@@ -183,6 +183,14 @@ def bench_interfaces(sh, xyz, out, steps):
     b = nc * (24 + 1600)
     res["complex"] = {"n_points": nc, "points_per_s": nc / avg, "kernel_ms": avg * 1e3, "gbs": b / avg / 1e9,
                       "frac": b / avg / 1e9 / HBM_PEAK_GBS, "bytes_per_point": 1624}
+    oc32 = out.view(-1)[: 100 * nc].view(torch.float32).view(torch.complex64).view(100, nc)
+    xc32 = xc.to(torch.float32)
+    _, per = time_launches(lambda: sh.sh_eval_complex_f32(9, xc32, out=oc32), steps, 2)
+    avg = sum(per) / len(per)
+    b = nc * (12 + 800)
+    res["complex_f32"] = {"n_points": nc, "points_per_s": nc / avg, "kernel_ms": avg * 1e3, "gbs": b / avg / 1e9,
+                          "frac": b / avg / 1e9 / HBM_PEAK_GBS, "bytes_per_point": 812}
+    del xc32
     # spinors: 200 (l, j, m_j) x 2 components x 16 B per point
     ns = n // 8
     os_ = out.view(-1)[: 800 * ns].view(torch.complex128).view(200, 2, ns)

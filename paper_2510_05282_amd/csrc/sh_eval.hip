@@ -109,71 +109,68 @@ hipError_t launch_fwd_angles(int lmax, int64_t n, const TIO* theta, const TIO* p
     return dispatch<TIO, In::kAngles>(lmax, n, {theta, phi}, out, ld, s);
 }
 
-template <int LMAX, typename TIO>
+// Complex and spinor kernels: 16 bytes per lane and row (one FP64 complex, or two
+// FP32 complex values of adjacent points), capped like the 16-byte real kernels.
+// FP32 outputs whose rows are not 16-byte aligned, and a last odd point, take
+// one point per lane.
+template <bool SPINOR, int LMAX, typename TIO, int PPL>
+static hipError_t launch_complex_one(int64_t n, const TIO* xyz, TIO* out, int64_t ld, hipStream_t s)
+{
+    const auto kernel = SPINOR ? fwd_spinor_kernel<LMAX, TIO, PPL> : fwd_complex_kernel<LMAX, TIO, PPL>;
+    const unsigned grid = unsigned((n / PPL + kFwdBlock - 1) / kFwdBlock);
+    const size_t lds = PPL * sizeof(TIO) * 2 == 16 ? kCapLds : 0;
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(kFwdBlock), lds, s, xyz, out, uint32_t(n), ld);
+    return hipGetLastError();
+}
+
+// out holds rows of ld complex values; a launch starting at point c0 writes from
+// out + 2 c0 (in TIO units).
+template <bool SPINOR, int LMAX, typename TIO>
 static hipError_t launch_complex_l(int64_t n, const TIO* xyz, TIO* out, int64_t ld, hipStream_t s)
 {
-    // one complex (two TIO) per lane and row: 16-byte stores in FP64, capped like the 16-byte real kernels
-    const size_t lds = sizeof(TIO) == 8 ? kCapLds : 0;
+    constexpr int kVec = sizeof(TIO) == 4 ? 2 : 1;
+    const bool vec_ok = ld % kVec == 0 && reinterpret_cast<uintptr_t>(out) % 16 == 0;
     for (int64_t c0 = 0; c0 < n; c0 += kChunk) {
         const int64_t nc = n - c0 < kChunk ? n - c0 : kChunk;
-        const unsigned grid = unsigned((nc + kFwdBlock - 1) / kFwdBlock);
-        hipLaunchKernelGGL((fwd_complex_kernel<LMAX, TIO>), dim3(grid), dim3(kFwdBlock), lds, s, xyz + 3 * c0,
-                           out + 2 * c0, uint32_t(nc), ld);
-        hipError_t e = hipGetLastError();
+        const int64_t nmain = vec_ok ? nc - nc % kVec : 0;
+        hipError_t e = hipSuccess;
+        if (nmain) e = launch_complex_one<SPINOR, LMAX, TIO, kVec>(nmain, xyz + 3 * c0, out + 2 * c0, ld, s);
+        if (e == hipSuccess && nmain < nc)
+            e = launch_complex_one<SPINOR, LMAX, TIO, 1>(nc - nmain, xyz + 3 * (c0 + nmain), out + 2 * (c0 + nmain),
+                                                         ld, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+template <bool SPINOR, typename TIO>
+static hipError_t dispatch_complex(int lmax, int64_t n, const TIO* xyz, TIO* out, int64_t ld, hipStream_t s)
+{
+    switch (lmax) {
+    case 0: return launch_complex_l<SPINOR, 0, TIO>(n, xyz, out, ld, s);
+    case 1: return launch_complex_l<SPINOR, 1, TIO>(n, xyz, out, ld, s);
+    case 2: return launch_complex_l<SPINOR, 2, TIO>(n, xyz, out, ld, s);
+    case 3: return launch_complex_l<SPINOR, 3, TIO>(n, xyz, out, ld, s);
+    case 4: return launch_complex_l<SPINOR, 4, TIO>(n, xyz, out, ld, s);
+    case 5: return launch_complex_l<SPINOR, 5, TIO>(n, xyz, out, ld, s);
+    case 6: return launch_complex_l<SPINOR, 6, TIO>(n, xyz, out, ld, s);
+    case 7: return launch_complex_l<SPINOR, 7, TIO>(n, xyz, out, ld, s);
+    case 8: return launch_complex_l<SPINOR, 8, TIO>(n, xyz, out, ld, s);
+    case 9: return launch_complex_l<SPINOR, 9, TIO>(n, xyz, out, ld, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 template <typename TIO>
 hipError_t launch_fwd_complex(int lmax, int64_t n, const TIO* xyz, TIO* out, int64_t ld, hipStream_t s)
 {
-    switch (lmax) {
-    case 0: return launch_complex_l<0, TIO>(n, xyz, out, ld, s);
-    case 1: return launch_complex_l<1, TIO>(n, xyz, out, ld, s);
-    case 2: return launch_complex_l<2, TIO>(n, xyz, out, ld, s);
-    case 3: return launch_complex_l<3, TIO>(n, xyz, out, ld, s);
-    case 4: return launch_complex_l<4, TIO>(n, xyz, out, ld, s);
-    case 5: return launch_complex_l<5, TIO>(n, xyz, out, ld, s);
-    case 6: return launch_complex_l<6, TIO>(n, xyz, out, ld, s);
-    case 7: return launch_complex_l<7, TIO>(n, xyz, out, ld, s);
-    case 8: return launch_complex_l<8, TIO>(n, xyz, out, ld, s);
-    case 9: return launch_complex_l<9, TIO>(n, xyz, out, ld, s);
-    default: return hipErrorInvalidValue;
-    }
-}
-
-template <int LMAX, typename TIO>
-static hipError_t launch_spinor_l(int64_t n, const TIO* xyz, TIO* out, int64_t ld, hipStream_t s)
-{
-    const size_t lds = sizeof(TIO) == 8 ? kCapLds : 0;
-    for (int64_t c0 = 0; c0 < n; c0 += kChunk) {
-        const int64_t nc = n - c0 < kChunk ? n - c0 : kChunk;
-        const unsigned grid = unsigned((nc + kFwdBlock - 1) / kFwdBlock);
-        hipLaunchKernelGGL((fwd_spinor_kernel<LMAX, TIO>), dim3(grid), dim3(kFwdBlock), lds, s, xyz + 3 * c0,
-                           out + 2 * c0, uint32_t(nc), ld);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    return dispatch_complex<false, TIO>(lmax, n, xyz, out, ld, s);
 }
 
 template <typename TIO>
 hipError_t launch_fwd_spinor(int lmax, int64_t n, const TIO* xyz, TIO* out, int64_t ld, hipStream_t s)
 {
-    switch (lmax) {
-    case 0: return launch_spinor_l<0, TIO>(n, xyz, out, ld, s);
-    case 1: return launch_spinor_l<1, TIO>(n, xyz, out, ld, s);
-    case 2: return launch_spinor_l<2, TIO>(n, xyz, out, ld, s);
-    case 3: return launch_spinor_l<3, TIO>(n, xyz, out, ld, s);
-    case 4: return launch_spinor_l<4, TIO>(n, xyz, out, ld, s);
-    case 5: return launch_spinor_l<5, TIO>(n, xyz, out, ld, s);
-    case 6: return launch_spinor_l<6, TIO>(n, xyz, out, ld, s);
-    case 7: return launch_spinor_l<7, TIO>(n, xyz, out, ld, s);
-    case 8: return launch_spinor_l<8, TIO>(n, xyz, out, ld, s);
-    case 9: return launch_spinor_l<9, TIO>(n, xyz, out, ld, s);
-    default: return hipErrorInvalidValue;
-    }
+    return dispatch_complex<true, TIO>(lmax, n, xyz, out, ld, s);
 }
 
 template hipError_t launch_fwd_spinor<double>(int, int64_t, const double*, double*, int64_t, hipStream_t);

@@ -90,52 +90,73 @@ __global__ __launch_bounds__(kFwdBlock) void fwd_kernel(const TIO* __restrict__ 
     });
 }
 
-// Complex harmonics from the real ones (Section 3): for m > 0
-//     Y_l^m  = (-1)^m (R_l^m + i R_l^-m) / sqrt(2),   Y_l^-m = (R_l^m - i R_l^-m) / sqrt(2),
-// and Y_l^0 = R_l^0.  (eq. real_harmomics inverted; the paper's printed relation
-// omits the 1/sqrt(2).)  Output: out[row][i] as (re, im) pairs, [F][ld] complex.
-// Each lane stores one complex value (two TIO) per row.
-template <int LMAX, typename TIO>
+// Loads PPL adjacent points (from point i0) as unit vectors in V lanes.
+template <typename TIO, int PPL, typename V>
+__device__ __forceinline__ void load_points(const TIO* __restrict__ xyz, uint32_t i0, V& x, V& y, V& z, V& k)
+{
+#pragma unroll
+    for (int q = 0; q < PPL; ++q) {
+        double xb, yb, zb, kb;
+        load_unit<In::kXyz, TIO>(xyz, nullptr, i0 + q, xb, yb, zb, kb);
+        lane<V, PPL>(x, q) = TIO(xb);
+        lane<V, PPL>(y, q) = TIO(yb);
+        lane<V, PPL>(z, q) = TIO(zb);
+        lane<V, PPL>(k, q) = TIO(kb);
+    }
+}
+
+// PPL complex values (re, im interleaved, PPL adjacent points) as one vector.
+template <typename TIO, int PPL, typename V>
+__device__ __forceinline__ typename vec_of<TIO, 2 * PPL>::type interleave(V re, V im)
+{
+    typename vec_of<TIO, 2 * PPL>::type w;
+#pragma unroll
+    for (int q = 0; q < PPL; ++q) {
+        w[2 * q] = lane<V, PPL>(re, q);
+        w[2 * q + 1] = lane<V, PPL>(im, q);
+    }
+    return w;
+}
+
+// Complex harmonics from the real ones (Section 3, complex_unit): out[row][i] as
+// (re, im) pairs, [F][ld] complex.  Each lane evaluates PPL adjacent points and
+// stores their PPL complex values of a row at once: 16 bytes per lane and row for
+// FP64 with PPL = 1 and FP32 with PPL = 2.  With PPL > 1 the host guarantees
+// n % PPL == 0, ld % PPL == 0 and a 16-byte aligned out.
+template <int LMAX, typename TIO, int PPL>
 __global__ __launch_bounds__(kFwdBlock) void fwd_complex_kernel(const TIO* __restrict__ xyz,
                                                                 TIO* __restrict__ out, uint32_t n, int64_t ld)
 {
-    using C = typename vec_of<TIO, 2>::type;
-    const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
-    const uint32_t i = b * kFwdBlock + threadIdx.x;
-    if (i >= n) return;
-    double xb, yb, zb, kb;
-    load_unit<In::kXyz, TIO>(xyz, nullptr, i, xb, yb, zb, kb);
-    const uint32_t boff = i * uint32_t(sizeof(C));
-    auto store = [&](int r, TIO re, TIO im) {
-        C v;
-        v.x = re;
-        v.y = im;
-        *reinterpret_cast<C*>(reinterpret_cast<char*>(reinterpret_cast<C*>(out) + int64_t(r) * ld) + boff) = v;
-    };
-    complex_unit<LMAX, TIO>(TIO(xb), TIO(yb), TIO(zb), TIO(kb),
-                            [&](int l, int m, TIO re, TIO im) { store(row(l, m), re, im); });
+    using V = typename vec_of<TIO, PPL>::type;
+    using W = typename vec_of<TIO, 2 * PPL>::type;
+    const uint32_t i0 = (xcd_tile(blockIdx.x, gridDim.x) * kFwdBlock + threadIdx.x) * PPL;
+    if (i0 >= n) return;
+    V x, y, z, k;
+    load_points<TIO, PPL>(xyz, i0, x, y, z, k);
+    const uint32_t boff = i0 * uint32_t(2 * sizeof(TIO));
+    complex_unit<LMAX, V>(x, y, z, k, [&](int l, int m, V re, V im) {
+        *reinterpret_cast<W*>(reinterpret_cast<char*>(out + 2 * int64_t(row(l, m)) * ld) + boff) =
+            interleave<TIO, PPL>(re, im);
+    });
 }
 
 // Spinor harmonics (eq. spinorial): spinor_unit's values, stored as they come to
-// out[(2 k + c) ld + i] as (re, im) pairs (c = 0 for the upper component).  One
-// complex value per lane and row, like the complex kernel.
-template <int LMAX, typename TIO>
+// out[(2 s + c) ld + i] as (re, im) pairs (c = 0 for the upper component), with
+// the same lanes as the complex kernel.
+template <int LMAX, typename TIO, int PPL>
 __global__ __launch_bounds__(kFwdBlock) void fwd_spinor_kernel(const TIO* __restrict__ xyz,
                                                                TIO* __restrict__ out, uint32_t n, int64_t ld)
 {
-    using C = typename vec_of<TIO, 2>::type;
-    const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
-    const uint32_t i = b * kFwdBlock + threadIdx.x;
-    if (i >= n) return;
-    double xb, yb, zb, kb;
-    load_unit<In::kXyz, TIO>(xyz, nullptr, i, xb, yb, zb, kb);
-    const uint32_t boff = i * uint32_t(sizeof(C));
-    spinor_unit<LMAX, TIO>(TIO(xb), TIO(yb), TIO(zb), TIO(kb), [&](int k, int c, TIO re, TIO im) {
-        C v;
-        v.x = re;
-        v.y = im;
-        *reinterpret_cast<C*>(reinterpret_cast<char*>(reinterpret_cast<C*>(out) + int64_t(2 * k + c) * ld) +
-                              boff) = v;
+    using V = typename vec_of<TIO, PPL>::type;
+    using W = typename vec_of<TIO, 2 * PPL>::type;
+    const uint32_t i0 = (xcd_tile(blockIdx.x, gridDim.x) * kFwdBlock + threadIdx.x) * PPL;
+    if (i0 >= n) return;
+    V x, y, z, k;
+    load_points<TIO, PPL>(xyz, i0, x, y, z, k);
+    const uint32_t boff = i0 * uint32_t(2 * sizeof(TIO));
+    spinor_unit<LMAX, V>(x, y, z, k, [&](int s, int c, V re, V im) {
+        *reinterpret_cast<W*>(reinterpret_cast<char*>(out + 2 * int64_t(2 * s + c) * ld) + boff) =
+            interleave<TIO, PPL>(re, im);
     });
 }
 

@@ -58,8 +58,10 @@ def test_appendix_d_points_on_gpu(dev, orc):
 
 
 @pytest.mark.parametrize("lmax", [0, 1, 4, 9])
-def test_complex_harmonics(dev, orc, lmax):
-    pts = workloads.points_plain_eval(seed=2, n_random=20000)
+@pytest.mark.parametrize("n_random", [20000, 19999])
+def test_complex_harmonics(dev, orc, lmax, n_random):
+    """FP32 runs two points per lane; an odd count ends with a one-point launch."""
+    pts = workloads.points_plain_eval(seed=2, n_random=n_random)
     got = sh.sh_eval_complex(lmax, torch.from_numpy(pts).to(dev)).cpu().numpy()
     re, im = orc.eval_complex_xyz(lmax, pts)
     assert np.abs(got.real.astype(LD) - re).max() <= 1e-13
@@ -72,8 +74,9 @@ def test_complex_harmonics(dev, orc, lmax):
 
 
 @pytest.mark.parametrize("lmax", [0, 1, 3, 9])
-def test_spinor_harmonics(dev, orc, lmax):
-    pts = workloads.points_plain_eval(seed=4, n_random=20000)
+@pytest.mark.parametrize("n_random", [20000, 19999])
+def test_spinor_harmonics(dev, orc, lmax, n_random):
+    pts = workloads.points_plain_eval(seed=4, n_random=n_random)
     got = sh.sh_eval_spinor(lmax, torch.from_numpy(pts).to(dev)).cpu().numpy()
     re, im = orc.eval_spinor_xyz(lmax, pts)
     assert got.shape == re.shape
