@@ -59,6 +59,9 @@ def _parse():
                     help="points of the oracle's CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="headline only")
+    ap.add_argument("--only", default="",
+                    help="comma-separated extra sections to run (sweep, interfaces, projectors, gradient, "
+                         "serving); default: all")
     ap.add_argument("--serve-requests", type=int, default=10_000)
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the headline, copy 4 GiB once (calibrates HBM traffic counters)")
@@ -430,7 +433,8 @@ def main():
                      "bytes_per_point": head["bytes_per_point"]},
     }
 
-    if not args.no_extras:
+    want = (lambda name: not args.no_extras and (not args.only or name in args.only.split(",")))
+    if want("sweep"):
         sweep = {}
         xyz32 = xyz.float()
         for lmax in (2, 4, 6, 9):
@@ -444,20 +448,23 @@ def main():
         result["write_probe"] = write_probe(out, 5)
         result["roofline"]["frac_of_write_probe"] = head["gbs"] / result["write_probe"]["gbs"]
         del xyz32
+    if want("interfaces"):
         _log("interfaces")
         result["interfaces"] = bench_interfaces(sh, xyz, out, max(5, args.steps // 2))
         _log("  ", json.dumps(result["interfaces"]))
 
     del out
     torch.cuda.empty_cache()
-    if not args.no_extras:
+    if want("projectors"):
         _log("projectors")
         result["projectors"] = bench_projectors(sh, workloads, dev, 20)
         _log("  ", json.dumps(result["projectors"]))
+    if want("gradient"):
         _log("gradient")
         result["gradient"] = bench_gradient(sh, workloads, dev, max(5, args.steps // 2))
         _log("  ", json.dumps(result["gradient"]))
         torch.cuda.empty_cache()
+    if want("serving"):
         _log("serving")
         result["serving"] = bench_serving(sh, workloads, dev, args.serve_requests)
         _log("  ", json.dumps(result["serving"]))
