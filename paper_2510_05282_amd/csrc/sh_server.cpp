@@ -176,15 +176,25 @@ void Server::finish_locked(int slot, int status)
     cv_done_.notify_all();
 }
 
-bool Server::reap_locked()
+// Finishes the batches that have completed.  Called with lk held; the completion
+// queries (HIP runtime calls) run with it released, so submitters are not held up
+// by them.  Only the scheduler thread launches, queries and finishes slots, so the
+// busy set cannot change while the lock is released.
+bool Server::reap(std::unique_lock<std::mutex>& lk)
 {
+    busy_.clear();
+    for (int s = 0; s < int(slot_reqs_.size()); ++s)
+        if (!slot_reqs_[s].empty()) busy_.push_back(s);
+    if (busy_.empty()) return false;
+    done_.assign(busy_.size(), 0);
+    lk.unlock();
+    for (size_t k = 0; k < busy_.size(); ++k) done_[k] = ex_->query(busy_[k]);
+    lk.lock();
     bool prog = false;
-    for (int s = 0; s < int(slot_reqs_.size()); ++s) {
-        if (slot_reqs_[s].empty()) continue;
-        const int q = ex_->query(s);
-        if (q == 0) continue;
+    for (size_t k = 0; k < busy_.size(); ++k) {
+        if (done_[k] == 0) continue;
         busy_slots_--;
-        finish_locked(s, q > 0 ? SH_OK : SH_EHIP);
+        finish_locked(busy_[k], done_[k] > 0 ? SH_OK : SH_EHIP);
         prog = true;
     }
     return prog;
@@ -194,7 +204,7 @@ void Server::loop()
 {
     std::unique_lock<std::mutex> lk(mu_);
     for (;;) {
-        bool prog = reap_locked();
+        bool prog = reap(lk);
         if (stop_) {
             // refuse what has not started; let running batches finish
             for (int64_t t : pending_) {
@@ -246,8 +256,19 @@ void Server::loop()
         }
         if (!prog) {
             if (busy_slots_ > 0) {
+                // Batches are running and nothing else can be done: poll their
+                // completion with the lock free until one finishes, or until a
+                // submit, release or shutdown bumps gen_ while a slot is free (with
+                // every slot busy, new work waits for a completion anyway, so
+                // submitters never contend with this thread for the lock).
+                // busy_ and free_slots_ change only on this thread.
+                const uint64_t g = gen_;
+                const bool slot_free = !free_slots_.empty();
                 lk.unlock();
-                std::this_thread::yield();
+                for (bool done = false; !done && !(gen_ != g && (slot_free || stop_));) {
+                    std::this_thread::yield();
+                    for (int s : busy_) done = done || ex_->query(s) != 0;
+                }
                 lk.lock();
             } else {
                 // nothing runs and nothing can be admitted: sleep until a submit,

@@ -18,6 +18,7 @@
 #include <stdint.h>
 
 #include <chrono>
+#include <atomic>
 #include <condition_variable>
 #include <deque>
 #include <map>
@@ -117,7 +118,7 @@ public:
 
 private:
     void loop();
-    bool reap_locked();
+    bool reap(std::unique_lock<std::mutex>& lk);
     bool admit_locked();
     void finish_locked(int slot, int status);
 
@@ -126,7 +127,7 @@ private:
     int64_t max_pending_;
     std::mutex mu_;
     std::condition_variable cv_work_, cv_done_;
-    bool stop_ = false;
+    std::atomic<bool> stop_{false};
     std::vector<Atom> atoms_;
     std::vector<Request> reqs_;
     std::deque<int64_t> pending_;
@@ -135,7 +136,8 @@ private:
     std::vector<int> free_slots_;
     int busy_slots_ = 0;
     int64_t refusals_ = 0;  // admission attempts refused for lack of budget
-    uint64_t gen_ = 0;      // bumped by every submit, release and shutdown
+    std::atomic<uint64_t> gen_{0};  // bumped by every submit, release and shutdown
+    std::vector<int> busy_, done_;  // scratch of reap(): busy slots and their query results
     std::vector<double> lat_ms_;
     Stats st_{};
     Clock::time_point t0_;
