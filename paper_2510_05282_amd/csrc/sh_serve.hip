@@ -2,7 +2,7 @@
 // batch on one of n_slots streams.
 //
 // A batch is a list of requests of any lmax and either dtype.  Each request is cut
-// into 256-point tiles; block b handles tile b of the batch, finds its request by
+// into tiles of kTilePoints points; block b handles tile b of the batch, finds its request by
 // a wave-wide search over the requests' first-tile indices, and runs the same
 // per-point projector evaluation as sh_projectors, dispatching once per block on
 // the request's (dtype, lmax).  Request descriptors travel host -> device through
@@ -60,8 +60,11 @@ __device__ __forceinline__ void serve_dispatch(const ServeDesc& d, int64_t j)
     }
 }
 
-__global__ __launch_bounds__(256) void serve_kernel(const ServeDesc* __restrict__ descs,
-                                                    const int64_t* __restrict__ tile0, int n_items)
+constexpr int kServeBlock = 256;
+constexpr int kTilePoints = 256;  // points per tile and block (a multiple of kServeBlock)
+
+__global__ __launch_bounds__(kServeBlock) void serve_kernel(const ServeDesc* __restrict__ descs,
+                                                            const int64_t* __restrict__ tile0, int n_items)
 {
     // Tiles are dealt round-robin to the XCDs (no XCD-contiguous remap): the cost of
     // a tile varies ~100x with its request's lmax, and interleaving keeps the XCDs'
@@ -69,10 +72,13 @@ __global__ __launch_bounds__(256) void serve_kernel(const ServeDesc* __restrict_
     const int64_t tile = blockIdx.x;
     // tile0 is increasing with tile0[0] = 0 <= tile, so the search finds an item
     const ServeDesc& d = descs[wave_search(tile0, n_items, tile)];
-    const int64_t j = (tile - d.tile0) * 256 + threadIdx.x;
-    if (j < 0 || j >= d.n) return;
-    if (d.dtype == SH_F64) serve_dispatch<double>(d, j);
-    else serve_dispatch<float>(d, j);
+    const int64_t j0 = (tile - d.tile0) * kTilePoints + threadIdx.x;
+    for (int q = 0; q < kTilePoints / kServeBlock; ++q) {
+        const int64_t j = j0 + q * kServeBlock;
+        if (j < 0 || j >= d.n) break;
+        if (d.dtype == SH_F64) serve_dispatch<double>(d, j);
+        else serve_dispatch<float>(d, j);
+    }
 }
 
 }  // namespace shk
@@ -118,6 +124,7 @@ public:
     int64_t max_items() const override { return kMaxItems; }
     // a dispatch counts its work-items in 32 bits: tiles * 256 < 2^32
     int64_t max_tiles() const override { return (int64_t(1) << 24) - 1; }
+    int64_t tile_points() const override { return shk::kTilePoints; }
     void* arena_base() override { return arena_; }
 
     int launch(int slot, const std::vector<Item>& items) override
@@ -144,7 +151,7 @@ public:
             d.ch = it.atom.tab_lmax + 1;
             d.lmax = it.lmax;
             d.dtype = it.atom.dtype;
-            tiles += (it.atom.n + 255) / 256;
+            tiles += (it.atom.n + shk::kTilePoints - 1) / shk::kTilePoints;
         }
         if (items.empty()) return SH_OK;
         if (tiles > max_tiles()) return SH_EINVAL;
@@ -155,8 +162,8 @@ public:
         if (e == hipSuccess)
             e = hipMemcpyAsync(dev_tile0, tile0, sizeof(int64_t) * items.size(), hipMemcpyHostToDevice, s.stream);
         if (e == hipSuccess) {
-            hipLaunchKernelGGL(shk::serve_kernel, dim3(unsigned(tiles)), dim3(256), 0, s.stream, s.dev, dev_tile0,
-                               int(items.size()));
+            hipLaunchKernelGGL(shk::serve_kernel, dim3(unsigned(tiles)), dim3(shk::kServeBlock), 0, s.stream, s.dev,
+                               dev_tile0, int(items.size()));
             e = hipGetLastError();
         }
         if (e == hipSuccess) e = hipEventRecord(s.done, s.stream);

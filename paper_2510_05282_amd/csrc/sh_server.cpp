@@ -88,7 +88,8 @@ Server::~Server()
 int Server::add_atom(const Atom& a, int* id)
 {
     if (!id || a.n <= 0 || !a.points || (a.dtype != SH_F64 && a.dtype != SH_F32)) return SH_EINVAL;
-    if ((a.n + 255) / 256 > ex_->max_tiles()) return SH_EINVAL;  // one batch could never hold it
+    const int64_t tp = ex_->tile_points();
+    if ((a.n + tp - 1) / tp > ex_->max_tiles()) return SH_EINVAL;  // one batch could never hold it
     std::lock_guard<std::mutex> g(mu_);
     atoms_.push_back(a);
     *id = int(atoms_.size() - 1);
@@ -232,7 +233,7 @@ void Server::loop()
             for (; k < queued_.size() && int64_t(items.size()) < ex_->max_items(); ++k) {
                 Request& r = reqs_[queued_[k]];
                 const Atom& a = atoms_[r.atom];
-                const int64_t nt = (a.n + 255) / 256;
+                const int64_t nt = (a.n + ex_->tile_points() - 1) / ex_->tile_points();
                 if (!items.empty() && tiles + nt > ex_->max_tiles()) break;
                 tiles += nt;
                 items.push_back(Item{a, r.lmax, at(ex_->arena_base(), r.offset)});
@@ -367,6 +368,7 @@ public:
     int n_slots() const override { return int(done_at_.size()); }
     int64_t max_items() const override { return 4096; }
     int64_t max_tiles() const override { return int64_t(1) << 22; }
+    int64_t tile_points() const override { return 256; }
     void* arena_base() override { return nullptr; }
     int launch(int slot, const std::vector<Item>& items) override
     {
