@@ -1,16 +1,20 @@
 // sh_serve.hip -- HIP executor of the projector server: one batched kernel per
 // batch on one of n_slots streams.
 //
-// A batch is a list of requests of any lmax and either dtype.  Each request is cut
-// into tiles of kTilePoints points; block b handles tile b of the batch, finds its request by
-// a wave-wide search over the requests' first-tile indices, and runs the same
-// per-point projector evaluation as sh_projectors, dispatching once per block on
-// the request's (dtype, lmax).  Request descriptors travel host -> device through
-// a pinned staging buffer per slot (the slot is reused only after its previous
-// batch has completed, so the staging buffer is never overwritten in flight).
+// A batch is a list of requests of any lmax and either dtype.  The requests are
+// grouped by (dtype, lmax) and each group gets one launch of the kernel built for
+// it (registers and occupancy sized for that lmax, no per-point dispatch); each
+// request is cut into 256-point tiles and every lane evaluates one point with the
+// same per-point projector code as sh_projectors.  Request descriptors and their
+// first-tile indices travel host -> device in one copy through a pinned staging
+// buffer per slot (the slot is reused only after its previous batch has completed,
+// so the staging buffer is never overwritten in flight).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
+
+#include <algorithm>
+#include <utility>
 
 #include "../../include/shmi.h"
 #include "sh_core.h"
@@ -42,43 +46,44 @@ __device__ __forceinline__ void serve_point(const ServeDesc& d, int64_t j)
                           static_cast<TIO*>(d.out) + j, d.n);
 }
 
-template <typename TIO>
-__device__ __forceinline__ void serve_dispatch(const ServeDesc& d, int64_t j)
-{
-    switch (d.lmax) {
-    case 0: serve_point<0, TIO>(d, j); break;
-    case 1: serve_point<1, TIO>(d, j); break;
-    case 2: serve_point<2, TIO>(d, j); break;
-    case 3: serve_point<3, TIO>(d, j); break;
-    case 4: serve_point<4, TIO>(d, j); break;
-    case 5: serve_point<5, TIO>(d, j); break;
-    case 6: serve_point<6, TIO>(d, j); break;
-    case 7: serve_point<7, TIO>(d, j); break;
-    case 8: serve_point<8, TIO>(d, j); break;
-    case 9: serve_point<9, TIO>(d, j); break;
-    default: break;
-    }
-}
+constexpr int kServeBlock = 256;  // points per tile and block
 
-constexpr int kServeBlock = 256;
-constexpr int kTilePoints = 256;  // points per tile and block (a multiple of kServeBlock)
-
+// One launch per (lmax, dtype) group of a batch: block b handles tile
+// xcd_tile(b) of the group (the tiles of one group cost the same, so
+// XCD-contiguous ranges stay balanced and each XCD keeps few requests' tables in
+// its L2), finds its request by a wave-wide search over the group's first-tile
+// indices and evaluates one point per lane.
+template <int LMAX, typename TIO>
 __global__ __launch_bounds__(kServeBlock) void serve_kernel(const ServeDesc* __restrict__ descs,
                                                             const int64_t* __restrict__ tile0, int n_items)
 {
-    // Tiles are dealt round-robin to the XCDs (no XCD-contiguous remap): the cost of
-    // a tile varies ~100x with its request's lmax, and interleaving keeps the XCDs'
-    // shares of a mixed batch even.
-    const int64_t tile = blockIdx.x;
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
     // tile0 is increasing with tile0[0] = 0 <= tile, so the search finds an item
     const ServeDesc& d = descs[wave_search(tile0, n_items, tile)];
-    const int64_t j0 = (tile - d.tile0) * kTilePoints + threadIdx.x;
-    for (int q = 0; q < kTilePoints / kServeBlock; ++q) {
-        const int64_t j = j0 + q * kServeBlock;
-        if (j < 0 || j >= d.n) break;
-        if (d.dtype == SH_F64) serve_dispatch<double>(d, j);
-        else serve_dispatch<float>(d, j);
+    const int64_t j = (tile - d.tile0) * kServeBlock + threadIdx.x;
+    if (j < 0 || j >= d.n) return;
+    serve_point<LMAX, TIO>(d, j);
+}
+
+template <typename TIO>
+static hipError_t launch_group(int lmax, int64_t tiles, const ServeDesc* descs, const int64_t* tile0, int n,
+                               hipStream_t s)
+{
+    const dim3 grid = dim3(unsigned(tiles)), block = dim3(kServeBlock);
+    switch (lmax) {
+    case 0: hipLaunchKernelGGL((serve_kernel<0, TIO>), grid, block, 0, s, descs, tile0, n); break;
+    case 1: hipLaunchKernelGGL((serve_kernel<1, TIO>), grid, block, 0, s, descs, tile0, n); break;
+    case 2: hipLaunchKernelGGL((serve_kernel<2, TIO>), grid, block, 0, s, descs, tile0, n); break;
+    case 3: hipLaunchKernelGGL((serve_kernel<3, TIO>), grid, block, 0, s, descs, tile0, n); break;
+    case 4: hipLaunchKernelGGL((serve_kernel<4, TIO>), grid, block, 0, s, descs, tile0, n); break;
+    case 5: hipLaunchKernelGGL((serve_kernel<5, TIO>), grid, block, 0, s, descs, tile0, n); break;
+    case 6: hipLaunchKernelGGL((serve_kernel<6, TIO>), grid, block, 0, s, descs, tile0, n); break;
+    case 7: hipLaunchKernelGGL((serve_kernel<7, TIO>), grid, block, 0, s, descs, tile0, n); break;
+    case 8: hipLaunchKernelGGL((serve_kernel<8, TIO>), grid, block, 0, s, descs, tile0, n); break;
+    case 9: hipLaunchKernelGGL((serve_kernel<9, TIO>), grid, block, 0, s, descs, tile0, n); break;
+    default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
 }
 
 }  // namespace shk
@@ -124,16 +129,29 @@ public:
     int64_t max_items() const override { return kMaxItems; }
     // a dispatch counts its work-items in 32 bits: tiles * 256 < 2^32
     int64_t max_tiles() const override { return (int64_t(1) << 24) - 1; }
-    int64_t tile_points() const override { return shk::kTilePoints; }
+    int64_t tile_points() const override { return shk::kServeBlock; }
     void* arena_base() override { return arena_; }
 
     int launch(int slot, const std::vector<Item>& items) override
     {
+        if (items.empty()) return SH_OK;
         Slot& s = slots_[slot];
-        int64_t* tile0 = reinterpret_cast<int64_t*>(s.host + kMaxItems);
+        const size_t n = items.size();
+        // items grouped by (dtype, lmax), in arrival order within a group
+        order_.resize(n);
+        for (size_t k = 0; k < n; ++k) order_[k] = int(k);
+        auto key = [&](int k) { return items[k].atom.dtype * 16 + items[k].lmax; };
+        std::stable_sort(order_.begin(), order_.end(), [&](int a, int b) { return key(a) < key(b); });
+        // descriptors, then their first-tile indices (relative to their group), in one copy
+        int64_t* tile0 = reinterpret_cast<int64_t*>(s.host + n);
+        groups_.clear();
         int64_t tiles = 0;
-        for (size_t k = 0; k < items.size(); ++k) {
-            const Item& it = items[k];
+        for (size_t k = 0; k < n; ++k) {
+            const Item& it = items[order_[k]];
+            if (groups_.empty() || key(order_[k]) != key(order_[groups_.back().first])) {
+                groups_.push_back({int(k), 0});
+                tiles = 0;
+            }
             shk::ServeDesc& d = s.host[k];
             memset(&d, 0, sizeof(d));
             d.points = it.atom.points;
@@ -151,20 +169,20 @@ public:
             d.ch = it.atom.tab_lmax + 1;
             d.lmax = it.lmax;
             d.dtype = it.atom.dtype;
-            tiles += (it.atom.n + shk::kTilePoints - 1) / shk::kTilePoints;
+            tiles += (it.atom.n + shk::kServeBlock - 1) / shk::kServeBlock;
+            groups_.back().second = tiles;
+            if (tiles > max_tiles()) return SH_EINVAL;
         }
-        if (items.empty()) return SH_OK;
-        if (tiles > max_tiles()) return SH_EINVAL;
-        // descriptors, then the first-tile index array at a fixed offset
-        hipError_t e = hipMemcpyAsync(s.dev, s.host, sizeof(shk::ServeDesc) * items.size(),
+        hipError_t e = hipMemcpyAsync(s.dev, s.host, (sizeof(shk::ServeDesc) + sizeof(int64_t)) * n,
                                       hipMemcpyHostToDevice, s.stream);
-        int64_t* dev_tile0 = reinterpret_cast<int64_t*>(s.dev + kMaxItems);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(dev_tile0, tile0, sizeof(int64_t) * items.size(), hipMemcpyHostToDevice, s.stream);
-        if (e == hipSuccess) {
-            hipLaunchKernelGGL(shk::serve_kernel, dim3(unsigned(tiles)), dim3(shk::kServeBlock), 0, s.stream, s.dev,
-                               dev_tile0, int(items.size()));
-            e = hipGetLastError();
+        const int64_t* dev_tile0 = reinterpret_cast<const int64_t*>(s.dev + n);
+        for (size_t g = 0; g < groups_.size() && e == hipSuccess; ++g) {
+            const int b = groups_[g].first;
+            const int m = (g + 1 < groups_.size() ? groups_[g + 1].first : int(n)) - b;
+            const shk::ServeDesc& d = s.host[b];
+            e = d.dtype == SH_F64
+                    ? shk::launch_group<double>(d.lmax, groups_[g].second, s.dev + b, dev_tile0 + b, m, s.stream)
+                    : shk::launch_group<float>(d.lmax, groups_[g].second, s.dev + b, dev_tile0 + b, m, s.stream);
         }
         if (e == hipSuccess) e = hipEventRecord(s.done, s.stream);
         return e == hipSuccess ? SH_OK : SH_EHIP;
@@ -180,7 +198,7 @@ public:
 
 private:
     static constexpr int64_t kMaxItems = 8192;
-    // per slot: kMaxItems descriptors followed by kMaxItems first-tile indices
+    // per slot: up to kMaxItems descriptors followed by as many first-tile indices
     static constexpr size_t kSlotBytes = (sizeof(shk::ServeDesc) + sizeof(int64_t)) * kMaxItems;
     struct Slot {
         hipStream_t stream = nullptr;
@@ -190,6 +208,8 @@ private:
     };
     std::vector<Slot> slots_;
     void* arena_ = nullptr;
+    std::vector<int> order_;                      // launch() scratch: items sorted by group
+    std::vector<std::pair<int, int64_t>> groups_;  // launch() scratch: (first item, tiles)
 };
 
 }  // namespace
