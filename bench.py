@@ -27,12 +27,16 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fwd_traffic.json")
 
 
 def fwd_source_hash() -> str:
-    """sha256 over the sources of the forward kernel (for matching counter data)."""
+    """sha256 over the code of the forward kernel's sources, comments and whitespace
+    removed (for matching counter data to the kernel they were taken on)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in FWD_SOURCES:
-        with open(os.path.join(ROOT, "paper_2510_05282_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2510_05282_amd", "csrc", f)) as fh:
+            code = re.sub(r"/\*.*?\*/", " ", fh.read(), flags=re.S)
+        code = re.sub(r"//[^\n]*", " ", code)
+        h.update(" ".join(code.split()).encode())
     return h.hexdigest()
 
 

@@ -188,8 +188,10 @@ __host__ __device__ __forceinline__ void complex_unit(T x, T y, T z, T keep, Sin
 
 // Spin-1/2 spinor harmonics (eq. spinorial) from the complex ones.  For orbital
 // l and total j = l +- 1/2,
-//     j = l + 1/2: upper =  sqrt((l + m_j + 1/2)/(2l+1)) Y_l^{m_j-1/2}, lower = sqrt((l - m_j + 1/2)/(2l+1)) Y_l^{m_j+1/2}
-//     j = l - 1/2: upper = -sqrt((l - m_j + 1/2)/(2l+1)) Y_l^{m_j-1/2}, lower = sqrt((l + m_j + 1/2)/(2l+1)) Y_l^{m_j+1/2}
+//     j = l + 1/2: upper =  sqrt((l + m_j + 1/2)/(2l+1)) Y_l^{m_j-1/2},
+//                  lower =  sqrt((l - m_j + 1/2)/(2l+1)) Y_l^{m_j+1/2},
+//     j = l - 1/2: upper = -sqrt((l - m_j + 1/2)/(2l+1)) Y_l^{m_j-1/2},
+//                  lower =  sqrt((l + m_j + 1/2)/(2l+1)) Y_l^{m_j+1/2},
 // with Y_l^m = 0 for |m| > l.  Each Y_l^m therefore feeds at most four
 // components with fixed coefficients and is passed on as soon as it is formed.
 // Spinor index k (l-major; j = l - 1/2 first; m_j ascending):

@@ -24,8 +24,8 @@ struct SplineGrid {
 //     S = A y_i + B y_{i+1} + ((A^3 - A) M_i + (B^3 - B) M_{i+1}) h^2/6;
 // 0 beyond r_max; a NaN r gives NaN.
 template <int NL, typename TIO>
-__host__ __device__ __forceinline__ void spline_eval(const double2* __restrict__ tab, int ch, const SplineGrid& g, double r,
-                                            TIO (&R)[NL])
+__host__ __device__ __forceinline__ void spline_eval(const double2* __restrict__ tab, int ch, const SplineGrid& g,
+                                                     double r, TIO (&R)[NL])
 {
     if (!(r <= g.r_max)) {
         const double v = r != r ? r : 0.0;

@@ -357,8 +357,9 @@ int64_t Server::latencies(double* out, int64_t cap)
 namespace {
 
 // Runs nothing: a launch takes launch_s of host time, a batch "finishes" after its
-// output bytes at a fixed rate, and every fail_every-th launch reports a failure.  Used to test scheduling without
-// a GPU; its arena has no memory (base address 0, offsets only).
+// output bytes at a fixed rate, and every fail_every-th launch reports a failure.
+// Used to test scheduling without a GPU; its arena has no memory (base address 0,
+// offsets only).
 class SimExecutor final : public Executor {
 public:
     SimExecutor(int n_slots, double bps, int fail_every, double launch_s)
