@@ -122,6 +122,18 @@ int sh_eval_spinor_f32(int lmax, int64_t n, const float *xyz, float *out, hipStr
 int sh_eval_grad(int lmax, int64_t n, const double *xyz, const double *grad_out, double *grad_xyz,
                  hipStream_t stream);
 
+/* Single-precision twin of sh_eval_grad: float xyz, grad_out and grad_xyz; the
+ * normalisation and 1/r in FP64, the polynomial gradients and the contraction
+ * over rows in FP32. */
+int sh_eval_grad_f32(int lmax, int64_t n, const float *xyz, const float *grad_out, float *grad_xyz,
+                     hipStream_t stream);
+
+/* Values and their Cartesian Jacobian in one pass, for forces:
+ *   out [F][n]      R_row(x_i)
+ *   jac [3][F][n]   d R_row(x_i) / d x_{i,k} at jac[(k * F + row) * n + i]
+ * (double).  Same derivative convention as sh_eval_grad; 0 at the origin. */
+int sh_eval_jac(int lmax, int64_t n, const double *xyz, double *out, double *jac, hipStream_t stream);
+
 /* ---------------------------------------------------------------------------
  * Projector build.  The paper's motivating use (Section 1): the angular part of
  * pseudopotential / PAW projectors on a real-space grid.  For atom a with centre
@@ -177,9 +189,9 @@ int sh_projectors_f32(int lmax, int n_atoms, const float *centers, const int64_t
  * projectors of one atom up to some lmax.  A scheduler thread admits pending
  * requests in arrival order while their output fits in an HBM budget (carved
  * from one device allocation made at creation), packs all admitted requests into
- * one batch and launches it on a free stream slot, so requests that arrive while
- * others run are admitted as memory and slots free up and their work overlaps on
- * the device.  Results stay on the device until released.  A request's latency
+ * one batch and launches it on a free stream slot (one kernel per (dtype, lmax)
+ * group of the batch), so requests that arrive while others run are admitted as
+ * memory and slots free up and their work overlaps on the device.  Results stay on the device until released.  A request's latency
  * is measured from sh_server_submit to the host seeing its batch complete.
  * Every function is thread-safe.
  */
@@ -256,18 +268,6 @@ int sh_server_stats(sh_server_t srv, sh_server_stats_t *out);
 /* Copies up to cap completed-request latencies (ms, completion order) into
  * out_ms (may be NULL) and returns how many there are (negative on error). */
 int64_t sh_server_latencies(sh_server_t srv, double *out_ms, int64_t cap);
-
-/* Single-precision twin of sh_eval_grad: float xyz, grad_out and grad_xyz; the
- * normalisation and 1/r in FP64, the polynomial gradients and the contraction
- * over rows in FP32. */
-int sh_eval_grad_f32(int lmax, int64_t n, const float *xyz, const float *grad_out, float *grad_xyz,
-                     hipStream_t stream);
-
-/* Values and their Cartesian Jacobian in one pass, for forces:
- *   out [F][n]      R_row(x_i)
- *   jac [3][F][n]   d R_row(x_i) / d x_{i,k} at jac[(k * F + row) * n + i]
- * (double).  Same derivative convention as sh_eval_grad; 0 at the origin. */
-int sh_eval_jac(int lmax, int64_t n, const double *xyz, double *out, double *jac, hipStream_t stream);
 
 /* Static text for a status code (never NULL). */
 const char *sh_strerror(int code);
