@@ -145,3 +145,37 @@ def test_projectors_across_launch_chunks(dev, orc):
         ref[:, sel] = ref_flat[F * sub_off[a]: F * sub_off[a] + F * m].reshape(F, m)
     rad.close()
     assert np.abs(got.astype(LD) - ref).max() <= 1e-13
+
+
+def test_inconsistent_offsets_are_skipped_in_bounds(dev, orc):
+    """Device-side offsets are not validated; a point whose atom range is
+    inconsistent (decreasing offsets, or an end beyond n_points) is skipped, and
+    nothing is written outside out[F * n_points] (a guard region after it stays
+    untouched).  Atoms with consistent ranges are still computed correctly."""
+    A = workloads.atom_spheres(seed=7, n_atoms=3, radius=1.2, h=0.3, lmax=2, n_r=200)
+    F, n = 9, A.points.shape[0]
+    assert n > 100
+    rad = sh.Radial(A.tables, A.r_max)
+    cen = torch.from_numpy(A.centers).to(dev)
+    pts = torch.from_numpy(A.points).to(dev)
+    sentinel = 12345.0
+    for offs in ([0, 40, 20, n], [0, 60, n + 500, n + 900], [5, 2, 1, n]):
+        big = torch.full((F * n + 4096,), sentinel, dtype=torch.float64, device=dev)
+        off = torch.tensor(offs, dtype=torch.int64, device=dev)
+        sh.sh_projectors(2, cen, off, pts, rad, out=big[: F * n])
+        torch.cuda.synchronize()
+        got = big.cpu().numpy()
+        assert np.all(got[F * n:] == sentinel), offs
+        written = got[: F * n] != sentinel
+        assert np.all(np.isfinite(got[: F * n][written]))
+    # only atom 0's range [0, 40) is consistent here (atom 1 ends beyond n_points):
+    # its block is exact and every other point is skipped
+    big = torch.full((F * n,), sentinel, dtype=torch.float64, device=dev)
+    off = torch.tensor([0, 40, n + 10, n + 20], dtype=torch.int64, device=dev)
+    sh.sh_projectors(2, cen, off, pts, rad, out=big)
+    torch.cuda.synchronize()
+    got = big.cpu().numpy()
+    ref = orc.projectors(2, A.centers[:1], np.array([0, 40]), A.points[:40], A.tables[:1], A.r_max)
+    assert np.abs(got[: F * 40].astype(LD) - ref).max() <= 1e-13
+    assert np.all(got[F * 40:] == sentinel)
+    rad.close()
