@@ -21,6 +21,7 @@ import sys
 import time
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector, published
 ROOT = os.path.dirname(os.path.abspath(__file__))
 FWD_SOURCES = ("sh_fwd.h", "sh_core.h", "sh_eval.hip", "sh_constants.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fwd_traffic.json")
@@ -40,17 +41,20 @@ def fwd_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per launch of the headline kernel from the committed rocprofv3
-    counter summary, or None when that summary was taken on other sources."""
+def counter_record():
+    """The committed rocprofv3 counter record of the headline kernel, or {} when it
+    was taken on other kernel code."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
-        return None
-    if t.get("source_sha256") != fwd_source_hash():
-        return None
-    return t.get("traffic_bytes_per_launch")
+        return {}
+    return t if t.get("source_sha256") == fwd_source_hash() else {}
+
+
+def measured_traffic():
+    """HBM bytes per launch of the headline kernel (counters), or None."""
+    return counter_record().get("traffic_bytes_per_launch")
 
 
 def _parse():
@@ -69,14 +73,30 @@ def _parse():
     ap.add_argument("--serve-requests", type=int, default=10_000)
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the headline, copy 4 GiB once (calibrates HBM traffic counters)")
-    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+    ap.add_argument("--traffic-from", nargs="+", metavar="CSV",
                     help="no GPU work: turn the counter_collection.csv files of a --pmc FETCH_SIZE and a "
-                         "--pmc WRITE_SIZE run of `--copy-probe` into the committed traffic record")
+                         "--pmc WRITE_SIZE run of `--copy-probe` (and optionally a --pmc "
+                         "SQ_INSTS_VALU_FLOPS_FP64 run) into the committed counter record")
     return ap.parse_args()
 
 
 HEADLINE_KERNEL = "shk::fwd_kernel<9, double, 2, (shk::In)0>"
 COPY_BYTES = 8 << 29  # the copy probe's 4 GiB
+
+
+def flops_from_counters(flops_csv: str) -> float:
+    """FP64 flops per launch of the headline kernel: SQ_INSTS_VALU_FLOPS_FP64 counts
+    the flops of each wave instruction once per wave, so it is scaled by the 64
+    lanes (averaged over the launches in the file)."""
+    import csv
+    acc = {}
+    with open(flops_csv, newline="") as fh:
+        for r in csv.DictReader(fh):
+            if r["Counter_Name"] == "SQ_INSTS_VALU_FLOPS_FP64" and HEADLINE_KERNEL in r["Kernel_Name"]:
+                acc[r["Dispatch_Id"]] = acc.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
+    if not acc:
+        raise SystemExit(f"{flops_csv}: no SQ_INSTS_VALU_FLOPS_FP64 rows for the headline kernel")
+    return 64.0 * sum(acc.values()) / len(acc)
 
 
 def traffic_from_counters(fetch_csv: str, write_csv: str, n_points: int) -> dict:
@@ -377,7 +397,11 @@ def cpu_baseline(pts, lmax, sample):
 def main():
     args = _parse()
     if args.traffic_from:
-        t = traffic_from_counters(*args.traffic_from, n_points=args.n)
+        if len(args.traffic_from) not in (2, 3):
+            raise SystemExit("--traffic-from takes FETCH_CSV WRITE_CSV [FLOPS_CSV]")
+        t = traffic_from_counters(*args.traffic_from[:2], n_points=args.n)
+        if len(args.traffic_from) == 3:
+            t["fp64_flops_per_launch"] = flops_from_counters(args.traffic_from[2])
         with open(TRAFFIC_FILE, "w") as fh:
             json.dump(t, fh, indent=1)
             fh.write("\n")
@@ -436,6 +460,14 @@ def main():
                      "kernel": HEADLINE_KERNEL, "kernel_ms": head["kernel_ms"],
                      "bytes_per_point": head["bytes_per_point"]},
     }
+    rec = counter_record()
+    if "fp64_flops_per_launch" in rec:
+        # FP64 VALU use: the counted flops of one launch over this run's launch time
+        tflops = rec["fp64_flops_per_launch"] / (head["kernel_ms"] * 1e-3) / 1e12
+        result["roofline"]["fp64_valu"] = {
+            "flops_per_point": rec["fp64_flops_per_launch"] / n, "tflops": tflops,
+            "peak_tflops": FP64_VECTOR_PEAK_TFLOPS, "frac": tflops / FP64_VECTOR_PEAK_TFLOPS,
+            "source": "SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes (rocprofv3, committed counter record)"}
 
     want = (lambda name: not args.no_extras and (not args.only or name in args.only.split(",")))
     if want("sweep"):
