@@ -358,6 +358,36 @@ def bench_serving(sh, workloads, dev, n_req):
     return out
 
 
+# The paper's own timings (Section 4, Table 1), in millions of individual
+# harmonics (point, l, m) per second, l <= 9, evaluated and accumulated rather than
+# stored, on one NVIDIA V100 and one core of an AMD Ryzen 5950X.
+PAPER_MHARM_PER_S = {
+    "real_cartesian": {"V100": 9939, "Ryzen 5950X, 1 core": 228},
+    "real_normalised": {"V100": 12540, "Ryzen 5950X, 1 core": 553},
+    "real_angular": {"V100": 9307, "Ryzen 5950X, 1 core": 159},
+    "complex_cartesian": {"V100": 5187, "Ryzen 5950X, 1 core": 85},
+}
+
+
+def paper_context(result: dict) -> dict:
+    """This run's rates in the paper's unit next to the paper's figures (context
+    only: other hardware, and the paper does not store its results)."""
+    mine = {"real_cartesian": result["value"] * 100 / 1e6}
+    itf = result.get("interfaces", {})
+    for key, name, per in (("unit", "real_normalised", 100), ("angles", "real_angular", 100),
+                           ("complex", "complex_cartesian", 100)):
+        if key in itf:
+            mine[name] = itf[key]["points_per_s"] * per / 1e6
+    out = {"unit": "M harmonics/s (lmax 9, FP64)", "paper": PAPER_MHARM_PER_S, "this_run_mi355x": mine,
+           "note": "paper: evaluated and accumulated in registers; this run: every value stored to HBM"}
+    if "cpu_baseline" in result:
+        cb = result["cpu_baseline"]
+        out["this_run_oracle_cpu"] = {"all_threads": cb["value"] * 100 / 1e6,
+                                      "one_thread": cb["one_thread_value"] * 100 / 1e6,
+                                      "note": "long-double test oracle, not an optimised CPU code"}
+    return out
+
+
 def _cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as fh:
@@ -509,6 +539,7 @@ def main():
     if not args.no_cpu_baseline:
         _log("cpu baseline")
         result["cpu_baseline"] = cpu_baseline(pts, 9, args.cpu_sample)
+    result["paper_context"] = paper_context(result)
     print(json.dumps(result), flush=True)
 
 
