@@ -140,6 +140,11 @@ def test_fp32_parity_per_l(dev, orc):
     err = np.abs(got.astype(LD) - ref).max(axis=1)
     _say("fp32 max abs err per l:", _per_l(err, 9))
     assert err.max() <= TOL32
+    # and against the plain FP64 kernel on the same GPU, at the same (float) points
+    got64 = _gpu(dev, 9, pts.astype(np.float64), torch.float64)
+    d = np.abs(got.astype(np.float64) - got64).max(axis=1)
+    _say("fp32 vs fp64 kernel, max abs diff per l:", _per_l(d, 9))
+    assert d.max() <= TOL32
 
 
 def test_bitwise_deterministic(dev):

@@ -140,6 +140,10 @@ def test_grad_fp32_parity(dev, orc):
         err = _rel_err(g.cpu().numpy(), ref)
         _say("  fp32 grad lmax", lmax, "max relative err:", float(err))
         assert err <= 2e-5
+        # and against the FP64 backward kernel on the same GPU at the same inputs
+        g64 = sh.sh_eval_grad(lmax, torch.from_numpy(pts.astype(np.float64)).to(dev),
+                              torch.from_numpy(G.astype(np.float64)).to(dev))
+        assert _rel_err(g.cpu().numpy(), g64.cpu().numpy()) <= 2e-5
 
 
 @pytest.mark.parametrize("extra", [0, 1])
