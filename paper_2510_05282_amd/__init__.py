@@ -20,7 +20,7 @@ SH_LMAX_REC = 24
 SH_F64 = 0
 SH_F32 = 1
 
-__all__ = ["SH_LMAX", "Radial", "ShError", "SphericalHarmonics", "nfun", "row", "sh_eval",
+__all__ = ["SH_F32", "SH_F64", "SH_LMAX", "SH_LMAX_REC", "Radial", "ShError", "SphericalHarmonics", "nfun", "row", "sh_eval",
            "sh_eval_angles", "sh_eval_angles_f32", "sh_eval_complex", "sh_eval_complex_f32",
            "sh_eval_spinor", "sh_eval_spinor_f32", "spinor_index",
            "sh_eval_f32", "sh_eval_grad", "sh_eval_grad_f32", "sh_eval_jac", "sh_eval_ld",
