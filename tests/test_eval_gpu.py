@@ -165,6 +165,18 @@ def test_tiny_and_huge_radii(dev, orc):
     assert np.abs(got.astype(LD) - ref).max() <= TOL64
 
 
+def test_tiny_huge_origin_fp32(dev, orc):
+    """FP32 inputs whose squares would under- or overflow in FP32 (the normalisation
+    runs in FP64), the exact origin and a NaN, against the oracle at the float inputs."""
+    base = workloads.isotropic_points(64, 1.0, 1.0, seed=19)
+    pts = np.concatenate([base * 1e-30, base * 1e30, base * 3e37, [[0, 0, 1e-37]], [[0, 0, 0]]]).astype(np.float32)
+    got = _gpu(dev, 9, pts, torch.float32)
+    assert np.abs(got.astype(LD) - orc.eval_xyz(9, pts)).max() <= TOL32
+    assert got[0, -1] != 0 and np.all(got[1:, -1] == 0)  # origin: only l = 0
+    nan = _gpu(dev, 4, np.array([[np.nan, 0, 1], [1, 2, 3]], dtype=np.float32), torch.float32)
+    assert np.isnan(nan[1:, 0]).all() and np.isfinite(nan[:, 1]).all()
+
+
 def test_nan_propagates(dev):
     pts = np.array([[np.nan, 0.0, 1.0], [1.0, 2.0, 3.0]])
     got = _gpu(dev, 4, pts)
