@@ -100,6 +100,10 @@ def test_interface_variants_validation(L):
         assert getattr(L, fn)(10, 5, fake, fake, None) == 1
         assert getattr(L, fn)(3, 5, None, fake, None) == 1
         assert getattr(L, fn)(3, 0, None, None, None) == 0
+    assert L.sh_eval_rec(25, 5, fake, fake, None) == 1  # beyond SH_LMAX_REC
+    assert L.sh_eval_rec(-1, 5, fake, fake, None) == 1
+    assert L.sh_eval_rec(24, 5, None, fake, None) == 1
+    assert L.sh_eval_rec(24, 0, None, None, None) == 0
     for fn in ("sh_eval_angles", "sh_eval_angles_f32"):
         assert getattr(L, fn)(10, 5, fake, fake, fake, None) == 1
         assert getattr(L, fn)(3, 5, fake, None, fake, None) == 1
