@@ -25,6 +25,11 @@ namespace shk {
 
 constexpr int kGradBlock = 256;
 constexpr int64_t kGradChunk = int64_t(1) << 28;
+// LDS reserved (not used) per workgroup of the backward kernel: at most 4 resident
+// workgroups (16 waves) per CU.  Measured on MI355X: 73% of 8 TB/s against 71.8%
+// uncapped (FP32: 74.1% against 71.0%).  Unlike the store-bound kernels, this
+// read-bound one runs best in plain workgroup order (XCD-contiguous order: 68.6%).
+constexpr size_t kGradCapLds = 40 * 1024;
 
 // TIO is the element type of xyz, G and the result; the normalisation and 1/r
 // run in FP64, the polynomials and the contraction in TIO.
@@ -59,8 +64,8 @@ static hipError_t launch_grad_l(int64_t n, const TIO* xyz, const TIO* G, int64_t
     for (int64_t c0 = 0; c0 < n; c0 += kGradChunk) {
         const int64_t nc = n - c0 < kGradChunk ? n - c0 : kGradChunk;
         const unsigned grid = unsigned((nc + kGradBlock - 1) / kGradBlock);
-        hipLaunchKernelGGL((grad_kernel<LMAX, TIO>), dim3(grid), dim3(kGradBlock), 0, s, xyz + 3 * c0, G + c0,
-                           gxyz + 3 * c0, uint32_t(nc), ldg);
+        hipLaunchKernelGGL((grad_kernel<LMAX, TIO>), dim3(grid), dim3(kGradBlock), kGradCapLds, s, xyz + 3 * c0,
+                           G + c0, gxyz + 3 * c0, uint32_t(nc), ldg);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
