@@ -185,7 +185,13 @@ public:
                     : shk::launch_group<float>(d.lmax, groups_[g].second, s.dev + b, dev_tile0 + b, m, s.stream);
         }
         if (e == hipSuccess) e = hipEventRecord(s.done, s.stream);
-        return e == hipSuccess ? SH_OK : SH_EHIP;
+        if (e != hipSuccess) {
+            // groups launched before the failure may still be writing into outputs the
+            // scheduler is about to release: let them finish first
+            (void)hipStreamSynchronize(s.stream);
+            return SH_EHIP;
+        }
+        return SH_OK;
     }
 
     int query(int slot) override
