@@ -52,6 +52,12 @@ enum sh_status {
 
 enum sh_dtype { SH_F64 = 0, SH_F32 = 1 };
 
+/* The paper's three input interfaces (Section 2), for the calls that take any:
+ *   SH_IN_XYZ     in0 = Cartesian points [n][3] (normalised here, origin convention)
+ *   SH_IN_UNIT    in0 = points on the unit sphere [n][3], used as given
+ *   SH_IN_ANGLES  in0 = polar angle theta[n], in1 = azimuth phi[n] (radians) */
+enum sh_input { SH_IN_XYZ = 0, SH_IN_UNIT = 1, SH_IN_ANGLES = 2 };
+
 /* Real harmonics in double precision.
  *   xyz: [n][3] double, out: [F][n] double (F = (lmax+1)^2).
  * Points are normalised in FP64 (hardware reciprocal square root refined by
@@ -97,6 +103,12 @@ int sh_eval_rec(int lmax, int64_t n, const double *xyz, double *out, hipStream_t
 int sh_eval_complex(int lmax, int64_t n, const double *xyz, double *out, hipStream_t stream);
 int sh_eval_complex_f32(int lmax, int64_t n, const float *xyz, float *out, hipStream_t stream);
 
+/* Complex harmonics from any input interface (enum sh_input) in dtype SH_F64 or
+ * SH_F32 (inputs and output alike); same output as sh_eval_complex.  SH_EINVAL
+ * also for an unknown input or dtype, or in1 NULL with SH_IN_ANGLES. */
+int sh_eval_complex_in(int lmax, int64_t n, int input, int dtype, const void *in0, const void *in1, void *out,
+                       hipStream_t stream);
+
 /* Spinor harmonics for spin 1/2 (eq. spinorial), built from the complex ones as
  * in Section 3: for orbital l and total j = l + 1/2 (l >= 0) or j = l - 1/2
  * (l >= 1), with m_j = -j .. j,
@@ -112,6 +124,10 @@ int sh_eval_complex_f32(int lmax, int64_t n, const float *xyz, float *out, hipSt
  * validation and origin convention as sh_eval_complex. */
 int sh_eval_spinor(int lmax, int64_t n, const double *xyz, double *out, hipStream_t stream);
 int sh_eval_spinor_f32(int lmax, int64_t n, const float *xyz, float *out, hipStream_t stream);
+
+/* Spinor harmonics from any input interface, as sh_eval_complex_in. */
+int sh_eval_spinor_in(int lmax, int64_t n, int input, int dtype, const void *in0, const void *in1, void *out,
+                      hipStream_t stream);
 
 /* Backward pass of sh_eval (vector-Jacobian product), for forces:
  *   grad_xyz[i][k] = sum_{row} grad_out[row][i] * d R_row(x_i) / d x_{i,k}

@@ -56,6 +56,7 @@ def lib():
         L.orc_projectors.argtypes = [i32, i32, vp, vp, vp, vp, i32, ctypes.c_double, vp, vp, vp]
         L.orc_num_threads.restype = i32
         L.orc_eval_complex_xyz.argtypes = [i32, i64, vp, vp, vp]
+        L.orc_eval_complex_angles.argtypes = [i32, i64, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -115,6 +116,18 @@ def eval_complex_xyz(lmax: int, xyz):
     return re, im
 
 
+def eval_complex_angles(lmax: int, theta, phi):
+    """Complex harmonics at polar angle theta and azimuth phi; returns (re, im),
+    each [F][n] long double."""
+    t = np.ascontiguousarray(np.atleast_1d(theta), dtype=LD)
+    f = np.ascontiguousarray(np.atleast_1d(phi), dtype=LD)
+    assert t.shape == f.shape
+    re = np.empty((nfun(lmax), t.shape[0]), dtype=LD)
+    im = np.empty_like(re)
+    _check(lib().orc_eval_complex_angles(lmax, t.shape[0], _p(t), _p(f), _p(re), _p(im)), "eval_complex_angles")
+    return re, im
+
+
 def spinor_index(l: int, kappa: int, twice_mj: int) -> int:
     """Index of the spinor harmonic with orbital l, j = l + kappa/2 (kappa = +1 or -1)
     and m_j = twice_mj / 2: l-major, j = l - 1/2 before j = l + 1/2, m_j ascending."""
@@ -131,7 +144,16 @@ def eval_spinor_xyz(lmax: int, xyz):
         upper = +- sqrt(l +- m_j + 1/2) Y_l^{m_j - 1/2} / sqrt(2l + 1)
         lower =    sqrt(l -+ m_j + 1/2) Y_l^{m_j + 1/2} / sqrt(2l + 1)
     with Y_l^m = 0 for |m| > l."""
-    re_y, im_y = eval_complex_xyz(lmax, xyz)
+    return _spinor_from_complex(lmax, *eval_complex_xyz(lmax, xyz))
+
+
+def eval_spinor_angles(lmax: int, theta, phi):
+    """Spinor harmonics at polar angle theta and azimuth phi, as eval_spinor_xyz."""
+    return _spinor_from_complex(lmax, *eval_complex_angles(lmax, theta, phi))
+
+
+def _spinor_from_complex(lmax: int, re_y, im_y):
+    """eq. spinorial applied to the complex harmonics re_y + i im_y [F][n]."""
     n = re_y.shape[1]
     ns = 2 * (lmax + 1) ** 2
     re = np.zeros((ns, 2, n), dtype=LD)

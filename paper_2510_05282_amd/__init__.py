@@ -22,7 +22,9 @@ SH_F32 = 1
 
 __all__ = ["SH_F32", "SH_F64", "SH_LMAX", "SH_LMAX_REC", "Radial", "ShError", "SphericalHarmonics", "nfun", "row", "sh_eval",
            "sh_eval_angles", "sh_eval_angles_f32", "sh_eval_complex", "sh_eval_complex_f32",
-           "sh_eval_spinor", "sh_eval_spinor_f32", "spinor_index",
+           "sh_eval_spinor", "sh_eval_spinor_f32", "spinor_index", "sh_eval_complex_unit",
+           "sh_eval_complex_angles", "sh_eval_spinor_unit", "sh_eval_spinor_angles",
+           "SH_IN_XYZ", "SH_IN_UNIT", "SH_IN_ANGLES",
            "sh_eval_f32", "sh_eval_grad", "sh_eval_grad_f32", "sh_eval_jac", "sh_eval_ld",
            "sh_eval_rec", "sh_eval_unit", "sh_eval_unit_f32",
            "sh_projectors", "sh_projectors_f32", "sh_radial_create", "sh_radial_destroy",
@@ -198,6 +200,53 @@ def sh_eval_spinor(lmax: int, xyz: torch.Tensor, out=None, stream=None) -> torch
 def sh_eval_spinor_f32(lmax: int, xyz: torch.Tensor, out=None, stream=None) -> torch.Tensor:
     """Spinor harmonics [2 (lmax+1)^2, 2, n] (complex64) of float32 points."""
     return _spinor("sh_eval_spinor_f32", torch.float32, torch.complex64, lmax, xyz, out, stream)
+
+
+SH_IN_XYZ, SH_IN_UNIT, SH_IN_ANGLES = 0, 1, 2
+
+
+def _cplx_in(fn: str, spinor: bool, lmax: int, input_kind: int, a: torch.Tensor, b, out, stream):
+    """Complex (spinor=False) or spinor harmonics through the any-input entry points;
+    the dtype (float64 -> complex128, float32 -> complex64) is taken from ``a``."""
+    code = _dtype_code(a.dtype)
+    if input_kind == SH_IN_ANGLES:
+        if not (a.is_cuda and isinstance(b, torch.Tensor) and b.is_cuda and a.dim() == 1 and b.shape == a.shape
+                and b.dtype == a.dtype and a.is_contiguous() and b.is_contiguous()):
+            raise ValueError("theta and phi must be contiguous 1-D CUDA tensors of one shape and dtype")
+        n = a.shape[0]
+    else:
+        n = _points(a, a.dtype)
+    ctype = torch.complex128 if a.dtype == torch.float64 else torch.complex64
+    shape = (2 * (lmax + 1) ** 2, 2, n) if spinor else (nfun(lmax), n)
+    if out is None:
+        out = torch.empty(shape, dtype=ctype, device=a.device)
+    elif out.dtype != ctype or tuple(out.shape) != shape or not out.is_contiguous():
+        raise ValueError(f"out must be a contiguous {list(shape)} {ctype} tensor")
+    with torch.cuda.device(a.device):
+        check(fn, getattr(lib(), fn)(lmax, n, input_kind, code, a.data_ptr(),
+                                     b.data_ptr() if input_kind == SH_IN_ANGLES else None, out.data_ptr(),
+                                     _stream(a.device, stream)))
+    return out
+
+
+def sh_eval_complex_unit(lmax: int, u: torch.Tensor, out=None, stream=None) -> torch.Tensor:
+    """Complex harmonics of points already on the unit sphere (float64 or float32)."""
+    return _cplx_in("sh_eval_complex_in", False, lmax, SH_IN_UNIT, u, None, out, stream)
+
+
+def sh_eval_complex_angles(lmax: int, theta: torch.Tensor, phi: torch.Tensor, out=None, stream=None):
+    """Complex harmonics at polar angles theta and azimuths phi (float64 or float32)."""
+    return _cplx_in("sh_eval_complex_in", False, lmax, SH_IN_ANGLES, theta, phi, out, stream)
+
+
+def sh_eval_spinor_unit(lmax: int, u: torch.Tensor, out=None, stream=None) -> torch.Tensor:
+    """Spinor harmonics of points already on the unit sphere."""
+    return _cplx_in("sh_eval_spinor_in", True, lmax, SH_IN_UNIT, u, None, out, stream)
+
+
+def sh_eval_spinor_angles(lmax: int, theta: torch.Tensor, phi: torch.Tensor, out=None, stream=None):
+    """Spinor harmonics at polar angles theta and azimuths phi."""
+    return _cplx_in("sh_eval_spinor_in", True, lmax, SH_IN_ANGLES, theta, phi, out, stream)
 
 
 def _grad(fn: str, dtype, lmax, xyz, grad_out, grad_xyz, stream):

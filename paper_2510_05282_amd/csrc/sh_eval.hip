@@ -113,20 +113,33 @@ hipError_t launch_fwd_angles(int lmax, int64_t n, const TIO* theta, const TIO* p
 // FP32 complex values of adjacent points), capped like the 16-byte real kernels.
 // FP32 outputs whose rows are not 16-byte aligned, and a last odd point, take
 // one point per lane.
+// Inputs of a complex or spinor launch: in0 (+ in1 for angles) and their kind.
+template <typename TIO>
+struct AnyInputs {
+    const TIO* a;
+    const TIO* b;
+    In mode;
+    AnyInputs at(int64_t c0) const
+    {
+        if (mode == In::kAngles) return {a + c0, b + c0, mode};
+        return {a + 3 * c0, b, mode};
+    }
+};
+
 template <bool SPINOR, int LMAX, typename TIO, int PPL>
-static hipError_t launch_complex_one(int64_t n, const TIO* xyz, TIO* out, int64_t ld, hipStream_t s)
+static hipError_t launch_complex_one(int64_t n, AnyInputs<TIO> in, TIO* out, int64_t ld, hipStream_t s)
 {
     const auto kernel = SPINOR ? fwd_spinor_kernel<LMAX, TIO, PPL> : fwd_complex_kernel<LMAX, TIO, PPL>;
     const unsigned grid = unsigned((n / PPL + kFwdBlock - 1) / kFwdBlock);
     const size_t lds = PPL * sizeof(TIO) * 2 == 16 ? kCapLds : 0;
-    hipLaunchKernelGGL(kernel, dim3(grid), dim3(kFwdBlock), lds, s, xyz, out, uint32_t(n), ld);
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(kFwdBlock), lds, s, in.a, out, uint32_t(n), ld, in.b, in.mode);
     return hipGetLastError();
 }
 
 // out holds rows of ld complex values; a launch starting at point c0 writes from
 // out + 2 c0 (in TIO units).
 template <bool SPINOR, int LMAX, typename TIO>
-static hipError_t launch_complex_l(int64_t n, const TIO* xyz, TIO* out, int64_t ld, hipStream_t s)
+static hipError_t launch_complex_l(int64_t n, AnyInputs<TIO> in, TIO* out, int64_t ld, hipStream_t s)
 {
     constexpr int kVec = sizeof(TIO) == 4 ? 2 : 1;
     const bool vec_ok = ld % kVec == 0 && reinterpret_cast<uintptr_t>(out) % 16 == 0;
@@ -134,17 +147,17 @@ static hipError_t launch_complex_l(int64_t n, const TIO* xyz, TIO* out, int64_t 
         const int64_t nc = n - c0 < kChunk ? n - c0 : kChunk;
         const int64_t nmain = vec_ok ? nc - nc % kVec : 0;
         hipError_t e = hipSuccess;
-        if (nmain) e = launch_complex_one<SPINOR, LMAX, TIO, kVec>(nmain, xyz + 3 * c0, out + 2 * c0, ld, s);
+        if (nmain) e = launch_complex_one<SPINOR, LMAX, TIO, kVec>(nmain, in.at(c0), out + 2 * c0, ld, s);
         if (e == hipSuccess && nmain < nc)
-            e = launch_complex_one<SPINOR, LMAX, TIO, 1>(nc - nmain, xyz + 3 * (c0 + nmain), out + 2 * (c0 + nmain),
-                                                         ld, s);
+            e = launch_complex_one<SPINOR, LMAX, TIO, 1>(nc - nmain, in.at(c0 + nmain), out + 2 * (c0 + nmain), ld,
+                                                         s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
 template <bool SPINOR, typename TIO>
-static hipError_t dispatch_complex(int lmax, int64_t n, const TIO* xyz, TIO* out, int64_t ld, hipStream_t s)
+static hipError_t dispatch_complex(int lmax, int64_t n, AnyInputs<TIO> xyz, TIO* out, int64_t ld, hipStream_t s)
 {
     switch (lmax) {
     case 0: return launch_complex_l<SPINOR, 0, TIO>(n, xyz, out, ld, s);
@@ -162,19 +175,23 @@ static hipError_t dispatch_complex(int lmax, int64_t n, const TIO* xyz, TIO* out
 }
 
 template <typename TIO>
-hipError_t launch_fwd_complex(int lmax, int64_t n, const TIO* xyz, TIO* out, int64_t ld, hipStream_t s)
+hipError_t launch_fwd_complex(int lmax, int64_t n, int input, const TIO* in0, const TIO* in1, TIO* out, int64_t ld,
+                              hipStream_t s)
 {
-    return dispatch_complex<false, TIO>(lmax, n, xyz, out, ld, s);
+    return dispatch_complex<false, TIO>(lmax, n, {in0, in1, In(input)}, out, ld, s);
 }
 
 template <typename TIO>
-hipError_t launch_fwd_spinor(int lmax, int64_t n, const TIO* xyz, TIO* out, int64_t ld, hipStream_t s)
+hipError_t launch_fwd_spinor(int lmax, int64_t n, int input, const TIO* in0, const TIO* in1, TIO* out, int64_t ld,
+                             hipStream_t s)
 {
-    return dispatch_complex<true, TIO>(lmax, n, xyz, out, ld, s);
+    return dispatch_complex<true, TIO>(lmax, n, {in0, in1, In(input)}, out, ld, s);
 }
 
-template hipError_t launch_fwd_spinor<double>(int, int64_t, const double*, double*, int64_t, hipStream_t);
-template hipError_t launch_fwd_spinor<float>(int, int64_t, const float*, float*, int64_t, hipStream_t);
+template hipError_t launch_fwd_spinor<double>(int, int64_t, int, const double*, const double*, double*, int64_t,
+                                             hipStream_t);
+template hipError_t launch_fwd_spinor<float>(int, int64_t, int, const float*, const float*, float*, int64_t,
+                                             hipStream_t);
 template hipError_t launch_fwd<double>(int, int64_t, const double*, double*, int64_t, hipStream_t);
 template hipError_t launch_fwd<float>(int, int64_t, const float*, float*, int64_t, hipStream_t);
 template hipError_t launch_fwd_unit<double>(int, int64_t, const double*, double*, int64_t, hipStream_t);
@@ -183,7 +200,9 @@ template hipError_t launch_fwd_angles<double>(int, int64_t, const double*, const
                                               hipStream_t);
 template hipError_t launch_fwd_angles<float>(int, int64_t, const float*, const float*, float*, int64_t,
                                              hipStream_t);
-template hipError_t launch_fwd_complex<double>(int, int64_t, const double*, double*, int64_t, hipStream_t);
-template hipError_t launch_fwd_complex<float>(int, int64_t, const float*, float*, int64_t, hipStream_t);
+template hipError_t launch_fwd_complex<double>(int, int64_t, int, const double*, const double*, double*, int64_t,
+                                             hipStream_t);
+template hipError_t launch_fwd_complex<float>(int, int64_t, int, const float*, const float*, float*, int64_t,
+                                             hipStream_t);
 
 }  // namespace shk

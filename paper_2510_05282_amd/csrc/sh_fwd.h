@@ -90,14 +90,18 @@ __global__ __launch_bounds__(kFwdBlock) void fwd_kernel(const TIO* __restrict__ 
     });
 }
 
-// Loads PPL adjacent points (from point i0) as unit vectors in V lanes.
+// Loads PPL adjacent points (from point i0) as unit vectors in V lanes; the input
+// interface is chosen at run time (the same for the whole launch).
 template <typename TIO, int PPL, typename V>
-__device__ __forceinline__ void load_points(const TIO* __restrict__ xyz, uint32_t i0, V& x, V& y, V& z, V& k)
+__device__ __forceinline__ void load_points(const TIO* __restrict__ in0, const TIO* __restrict__ in1, In mode,
+                                            uint32_t i0, V& x, V& y, V& z, V& k)
 {
 #pragma unroll
     for (int q = 0; q < PPL; ++q) {
         double xb, yb, zb, kb;
-        load_unit<In::kXyz, TIO>(xyz, nullptr, i0 + q, xb, yb, zb, kb);
+        if (mode == In::kXyz) load_unit<In::kXyz, TIO>(in0, in1, i0 + q, xb, yb, zb, kb);
+        else if (mode == In::kUnit) load_unit<In::kUnit, TIO>(in0, in1, i0 + q, xb, yb, zb, kb);
+        else load_unit<In::kAngles, TIO>(in0, in1, i0 + q, xb, yb, zb, kb);
         lane<V, PPL>(x, q) = TIO(xb);
         lane<V, PPL>(y, q) = TIO(yb);
         lane<V, PPL>(z, q) = TIO(zb);
@@ -122,17 +126,19 @@ __device__ __forceinline__ typename vec_of<TIO, 2 * PPL>::type interleave(V re, 
 // (re, im) pairs, [F][ld] complex.  Each lane evaluates PPL adjacent points and
 // stores their PPL complex values of a row at once: 16 bytes per lane and row for
 // FP64 with PPL = 1 and FP32 with PPL = 2.  With PPL > 1 the host guarantees
-// n % PPL == 0, ld % PPL == 0 and a 16-byte aligned out.
+// n % PPL == 0, ld % PPL == 0 and a 16-byte aligned out.  Inputs as for fwd_kernel:
+// in0 = xyz [n][3] (kXyz, kUnit) or theta[n] and in1 = phi[n] (kAngles).
 template <int LMAX, typename TIO, int PPL>
-__global__ __launch_bounds__(kFwdBlock) void fwd_complex_kernel(const TIO* __restrict__ xyz,
-                                                                TIO* __restrict__ out, uint32_t n, int64_t ld)
+__global__ __launch_bounds__(kFwdBlock) void fwd_complex_kernel(const TIO* __restrict__ in0,
+                                                                TIO* __restrict__ out, uint32_t n, int64_t ld,
+                                                                const TIO* __restrict__ in1, In mode)
 {
     using V = typename vec_of<TIO, PPL>::type;
     using W = typename vec_of<TIO, 2 * PPL>::type;
     const uint32_t i0 = (xcd_tile(blockIdx.x, gridDim.x) * kFwdBlock + threadIdx.x) * PPL;
     if (i0 >= n) return;
     V x, y, z, k;
-    load_points<TIO, PPL>(xyz, i0, x, y, z, k);
+    load_points<TIO, PPL>(in0, in1, mode, i0, x, y, z, k);
     const uint32_t boff = i0 * uint32_t(2 * sizeof(TIO));
     complex_unit<LMAX, V>(x, y, z, k, [&](int l, int m, V re, V im) {
         *reinterpret_cast<W*>(reinterpret_cast<char*>(out + 2 * int64_t(row(l, m)) * ld) + boff) =
@@ -144,15 +150,16 @@ __global__ __launch_bounds__(kFwdBlock) void fwd_complex_kernel(const TIO* __res
 // out[(2 s + c) ld + i] as (re, im) pairs (c = 0 for the upper component), with
 // the same lanes as the complex kernel.
 template <int LMAX, typename TIO, int PPL>
-__global__ __launch_bounds__(kFwdBlock) void fwd_spinor_kernel(const TIO* __restrict__ xyz,
-                                                               TIO* __restrict__ out, uint32_t n, int64_t ld)
+__global__ __launch_bounds__(kFwdBlock) void fwd_spinor_kernel(const TIO* __restrict__ in0,
+                                                               TIO* __restrict__ out, uint32_t n, int64_t ld,
+                                                               const TIO* __restrict__ in1, In mode)
 {
     using V = typename vec_of<TIO, PPL>::type;
     using W = typename vec_of<TIO, 2 * PPL>::type;
     const uint32_t i0 = (xcd_tile(blockIdx.x, gridDim.x) * kFwdBlock + threadIdx.x) * PPL;
     if (i0 >= n) return;
     V x, y, z, k;
-    load_points<TIO, PPL>(xyz, i0, x, y, z, k);
+    load_points<TIO, PPL>(in0, in1, mode, i0, x, y, z, k);
     const uint32_t boff = i0 * uint32_t(2 * sizeof(TIO));
     spinor_unit<LMAX, V>(x, y, z, k, [&](int s, int c, V re, V im) {
         *reinterpret_cast<W*>(reinterpret_cast<char*>(out + 2 * int64_t(2 * s + c) * ld) + boff) =

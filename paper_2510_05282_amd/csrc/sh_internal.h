@@ -26,16 +26,20 @@ template <typename TIO>
 hipError_t launch_fwd_angles(int lmax, int64_t n, const TIO* theta, const TIO* phi, TIO* out, int64_t ld,
                              hipStream_t s);
 // Complex harmonics Y_l^m into out[F][ld] of (re, im) pairs (ld in complex elements).
+// input: 0 = Cartesian xyz in0 [n][3], 1 = unit vectors in0 [n][3], 2 = angles
+// theta = in0[n], phi = in1[n] (the values of In and of sh_input).
 template <typename TIO>
-hipError_t launch_fwd_complex(int lmax, int64_t n, const TIO* xyz, TIO* out, int64_t ld, hipStream_t s);
+hipError_t launch_fwd_complex(int lmax, int64_t n, int input, const TIO* in0, const TIO* in1, TIO* out, int64_t ld,
+                              hipStream_t s);
 
 // Vector-Jacobian product: gxyz[n][3] = sum_f G[f][i] dR_f/dx at xyz[n][3]; G is [F][ldg].
 template <typename TIO>
 hipError_t launch_grad(int lmax, int64_t n, const TIO* xyz, const TIO* G, int64_t ldg, TIO* gxyz, hipStream_t s);
 
-// Spinor harmonics into out[2 (lmax+1)^2][2][ld] of (re, im) pairs.
+// Spinor harmonics into out[2 (lmax+1)^2][2][ld] of (re, im) pairs; inputs as above.
 template <typename TIO>
-hipError_t launch_fwd_spinor(int lmax, int64_t n, const TIO* xyz, TIO* out, int64_t ld, hipStream_t s);
+hipError_t launch_fwd_spinor(int lmax, int64_t n, int input, const TIO* in0, const TIO* in1, TIO* out, int64_t ld,
+                             hipStream_t s);
 
 // Real harmonics up to lmax <= SH_LMAX_REC by recurrence (FP64).
 hipError_t launch_rec(int lmax, int64_t n, const double* xyz, double* out, int64_t ld, hipStream_t s);

@@ -100,6 +100,14 @@ def test_interface_variants_validation(L):
         assert getattr(L, fn)(10, 5, fake, fake, None) == 1
         assert getattr(L, fn)(3, 5, None, fake, None) == 1
         assert getattr(L, fn)(3, 0, None, None, None) == 0
+    for fn in ("sh_eval_complex_in", "sh_eval_spinor_in"):
+        f = getattr(L, fn)
+        assert f(3, 5, 3, 0, fake, fake, fake, None) == 1     # unknown input kind
+        assert f(3, 5, 0, 2, fake, fake, fake, None) == 1     # unknown dtype
+        assert f(3, 5, 2, 0, fake, None, fake, None) == 1     # angles need phi
+        assert f(10, 5, 1, 1, fake, None, fake, None) == 1    # lmax
+        assert f(3, 5, 1, 0, None, None, fake, None) == 1
+        assert f(3, 0, 2, 1, None, None, None, None) == 0     # n == 0
     assert L.sh_eval_rec(25, 5, fake, fake, None) == 1  # beyond SH_LMAX_REC
     assert L.sh_eval_rec(-1, 5, fake, fake, None) == 1
     assert L.sh_eval_rec(24, 5, None, fake, None) == 1

@@ -105,3 +105,32 @@ def test_recurrence_beyond_l9(dev, orc, lmax, n_random):
     if lmax <= 9:  # agrees with the explicit formulas
         ex = sh.sh_eval(lmax, torch.from_numpy(pts).to(dev)).cpu().numpy()
         assert np.abs(got - ex).max() <= 2e-14
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_complex_and_spinor_other_inputs(dev, orc, dtype):
+    """Complex and spinor harmonics through the unit-vector and angular interfaces
+    (paper Section 2), odd and even counts, against the oracle's complex harmonics
+    at the same unit vectors and angles."""
+    tol = 1e-13 if dtype == np.float64 else 5e-6
+    for n in (1001, 1000):
+        u = _units(n, 70 + n, dtype)
+        re, im = orc.eval_complex_xyz(9, u.astype(np.float64))
+        got = sh.sh_eval_complex_unit(9, torch.from_numpy(u).to(dev)).cpu().numpy()
+        assert np.abs(got.real.astype(LD) - re).max() <= tol
+        assert np.abs(got.imag.astype(LD) - im).max() <= tol
+        sre, sim = orc.eval_spinor_xyz(9, u.astype(np.float64))
+        gs = sh.sh_eval_spinor_unit(9, torch.from_numpy(u).to(dev)).cpu().numpy()
+        assert np.abs(gs.real.astype(LD) - sre).max() <= tol
+        assert np.abs(gs.imag.astype(LD) - sim).max() <= tol
+        rng = np.random.default_rng(n)
+        th = np.concatenate([np.arccos(rng.uniform(-1, 1, n - 2)), [0.0, np.pi]]).astype(dtype)
+        ph = rng.uniform(-np.pi, np.pi, n).astype(dtype)
+        re, im = orc.eval_complex_angles(9, th.astype(LD), ph.astype(LD))
+        got = sh.sh_eval_complex_angles(9, torch.from_numpy(th).to(dev), torch.from_numpy(ph).to(dev)).cpu().numpy()
+        assert np.abs(got.real.astype(LD) - re).max() <= tol
+        assert np.abs(got.imag.astype(LD) - im).max() <= tol
+        sre, sim = orc.eval_spinor_angles(9, th.astype(LD), ph.astype(LD))
+        gs = sh.sh_eval_spinor_angles(9, torch.from_numpy(th).to(dev), torch.from_numpy(ph).to(dev)).cpu().numpy()
+        assert np.abs(gs.real.astype(LD) - sre).max() <= tol
+        assert np.abs(gs.imag.astype(LD) - sim).max() <= tol

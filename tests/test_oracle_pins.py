@@ -412,3 +412,21 @@ def test_library_routine_std_sph_legendre(orc, tmp_path):
                 s = math.sqrt(2.0) * (-1) ** m
                 assert np.abs(got[_row(l, m)] - s * y * np.cos(m * ph)).max() <= 1e-14
                 assert np.abs(got[_row(l, -m)] - s * y * np.sin(m * ph)).max() <= 1e-14
+
+
+def test_complex_from_angles_mpmath(orc):
+    """The angular entry of the complex oracle against mpmath's spherharm, which
+    takes (theta, phi) directly; poles and azimuths in every quadrant included."""
+    mp.mp.dps = 40
+    rng = np.random.default_rng(55)
+    th = np.concatenate([np.arccos(rng.uniform(-1, 1, 10)), [0.0, np.pi, 1e-9, np.pi / 2]])
+    ph = np.concatenate([rng.uniform(-np.pi, np.pi, 10), [0.3, -2.5, 3.0, -0.7]])
+    re, im = orc.eval_complex_angles(9, th.astype(LD), ph.astype(LD))
+    for i in range(th.shape[0]):
+        t, p = _mpf(LD(th[i])), _mpf(LD(ph[i]))
+        for l in range(10):
+            for m in range(-l, l + 1):
+                ref = mp.spherharm(l, m, t, p)
+                r = _row(l, m)
+                assert abs(_mpf(re[r, i]) - mp.re(ref)) <= 2e-17
+                assert abs(_mpf(im[r, i]) - mp.im(ref)) <= 2e-17
