@@ -94,6 +94,11 @@ int sh_eval_angles_f32(int lmax, int64_t n, const float *theta, const float *phi
  * same normalisation, origin guard and [F][n] layout as sh_eval (double). */
 int sh_eval_rec(int lmax, int64_t n, const double *xyz, double *out, hipStream_t stream);
 
+/* Single-precision twin of sh_eval_rec (normalisation in FP64, recurrence in FP32).
+ * Max abs error against the exact value at the float inputs: 5e-6 for l <= 9,
+ * 1e-6 (l + 1) beyond (the recurrence accumulates rounding with l). */
+int sh_eval_rec_f32(int lmax, int64_t n, const float *xyz, float *out, hipStream_t stream);
+
 /* Complex harmonics Y_l^m (eq. sphericalfromlegendre, with the Condon-Shortley
  * phase), built from the real ones (Section 3): Y_l^0 = R_l^0 and, for m > 0,
  *   Y_l^m = (-1)^m (R_l^m + i R_l^-m) / sqrt(2),   Y_l^-m = (R_l^m - i R_l^-m) / sqrt(2)

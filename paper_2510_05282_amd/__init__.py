@@ -26,7 +26,7 @@ __all__ = ["SH_F32", "SH_F64", "SH_LMAX", "SH_LMAX_REC", "Radial", "ShError", "S
            "sh_eval_complex_angles", "sh_eval_spinor_unit", "sh_eval_spinor_angles",
            "SH_IN_XYZ", "SH_IN_UNIT", "SH_IN_ANGLES",
            "sh_eval_f32", "sh_eval_grad", "sh_eval_grad_f32", "sh_eval_jac", "sh_eval_ld",
-           "sh_eval_rec", "sh_eval_unit", "sh_eval_unit_f32",
+           "sh_eval_rec", "sh_eval_rec_f32", "sh_eval_unit", "sh_eval_unit_f32",
            "sh_projectors", "sh_projectors_f32", "sh_radial_create", "sh_radial_destroy",
            "sh_strerror", "spherical_harmonics"]
 
@@ -109,6 +109,11 @@ def sh_eval_f32(lmax: int, xyz: torch.Tensor, out: torch.Tensor | None = None,
 def sh_eval_rec(lmax: int, xyz: torch.Tensor, out: torch.Tensor | None = None, stream=None):
     """Real harmonics for lmax <= 24 by recurrence (float64), layout as sh_eval."""
     return _eval("sh_eval_rec", torch.float64, lmax, xyz, out, stream)
+
+
+def sh_eval_rec_f32(lmax: int, xyz: torch.Tensor, out: torch.Tensor | None = None, stream=None):
+    """Single-precision twin of sh_eval_rec (normalisation in FP64)."""
+    return _eval("sh_eval_rec_f32", torch.float32, lmax, xyz, out, stream)
 
 
 def sh_eval_unit(lmax: int, xyz: torch.Tensor, out: torch.Tensor | None = None, stream=None):

@@ -53,7 +53,7 @@ def lib() -> ctypes.CDLL:
     L.sh_eval_f32.restype = i32
     L.sh_eval_ld.argtypes = [i32, i64, vp, vp, i64, i32, vp]
     L.sh_eval_ld.restype = i32
-    for fn in ("sh_eval_unit", "sh_eval_unit_f32", "sh_eval_complex", "sh_eval_complex_f32", "sh_eval_rec",
+    for fn in ("sh_eval_unit", "sh_eval_unit_f32", "sh_eval_complex", "sh_eval_complex_f32", "sh_eval_rec", "sh_eval_rec_f32",
                "sh_eval_spinor", "sh_eval_spinor_f32"):
         getattr(L, fn).argtypes = [i32, i64, vp, vp, vp]
         getattr(L, fn).restype = i32

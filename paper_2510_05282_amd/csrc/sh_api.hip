@@ -178,7 +178,15 @@ int sh_eval_rec(int lmax, int64_t n, const double *xyz, double *out, hipStream_t
     if (lmax < 0 || lmax > SH_LMAX_REC || n < 0) return SH_EINVAL;
     if (n == 0) return SH_OK;
     if (!xyz || !out) return SH_EINVAL;
-    return hip_status(shk::launch_rec(lmax, n, xyz, out, n, stream));
+    return hip_status(shk::launch_rec<double>(lmax, n, xyz, out, n, stream));
+}
+
+int sh_eval_rec_f32(int lmax, int64_t n, const float *xyz, float *out, hipStream_t stream)
+{
+    if (lmax < 0 || lmax > SH_LMAX_REC || n < 0) return SH_EINVAL;
+    if (n == 0) return SH_OK;
+    if (!xyz || !out) return SH_EINVAL;
+    return hip_status(shk::launch_rec<float>(lmax, n, xyz, out, n, stream));
 }
 
 int sh_eval(int lmax, int64_t n, const double *xyz, double *out, hipStream_t stream)

@@ -18,25 +18,26 @@ namespace shk {
 template <typename T, typename Store>
 __host__ __device__ __forceinline__ void eval_unit_rec(T x, T y, T z, T keep, int lmax, Store&& store)
 {
-    T c = T(1.0), s = T(0.0);  // C_m + i S_m = (x + i y)^m
+    using S = scalar_t<T>;     // coefficients are rounded once to the arithmetic type
+    T c = T(S(1)), s = T(S(0));  // C_m + i S_m = (x + i y)^m
     for (int m = 0; m <= lmax; ++m) {
         if (m > 0) {
             const T cn = x * c - y * s;
             s = x * s + y * c;
             c = cn;
         }
-        const double d = shc::kRecD[m];
-        T y2 = T(0.0), y1 = T(d);  // Yb_{l-2}^m, Yb_{l-1}^m
+        const S d = S(shc::kRecD[m]);
+        T y2 = T(S(0)), y1 = T(d);  // Yb_{l-2}^m, Yb_{l-1}^m
         for (int l = m; l <= lmax; ++l) {
             T yl;
             if (l == m) {
                 yl = T(d);
             } else if (l == m + 1) {
-                yl = shc::kRecE[m] * z * d;
+                yl = S(shc::kRecE[m]) * z * d;
                 y2 = y1;
                 y1 = yl;
             } else {
-                yl = shc::kRecA[l][m] * (z * y1 - shc::kRecB[l][m] * y2);
+                yl = S(shc::kRecA[l][m]) * (z * y1 - S(shc::kRecB[l][m]) * y2);
                 y2 = y1;
                 y1 = yl;
             }

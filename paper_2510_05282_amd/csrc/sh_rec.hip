@@ -13,10 +13,11 @@
 //     a_lm = sqrt((4l^2 - 1)/(l^2 - m^2)),  b_lm = sqrt(((l-1)^2 - m^2)/(4(l-1)^2 - 1)),
 // whose coefficients are generated once (gen_rec_constants.py, 50-digit mpmath),
 // so the kernel does no square roots or divisions.  Same normalisation, origin
-// guard and [F][ld] layout as the explicit kernels, FP64, lmax up to
-// SH_LMAX_REC.  The launch follows the explicit kernel's: two adjacent points per
-// lane with 16-byte row stores, XCD-contiguous workgroups, at most 2 resident
-// workgroups per CU; one point per lane for odd ld or a remainder point.
+// guard and [F][ld] layout as the explicit kernels, FP64 or FP32 (normalisation
+// in FP64 either way), lmax up to SH_LMAX_REC.  The launch follows the explicit
+// kernel's: 16-byte row stores per lane (two FP64 or four FP32 adjacent points),
+// XCD-contiguous workgroups, at most 2 resident workgroups per CU; one point per
+// lane for an unaligned row stride or the remainder points.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -24,6 +25,7 @@
 
 #include "../../include/shmi.h"
 #include "sh_core.h"
+#include "sh_fwd.h"
 #include "sh_internal.h"
 #include "sh_rec.h"
 
@@ -35,53 +37,50 @@ constexpr int kRecBlock = 256;
 constexpr int64_t kRecChunk = int64_t(1) << 28;
 constexpr size_t kRecCapLds = 54 * 1024;
 
-template <int PPL>
-__global__ __launch_bounds__(kRecBlock) void rec_kernel(const double* __restrict__ xyz, double* __restrict__ out,
+// TIO = double: 2 points per lane (PPL = 2); float: 4 (PPL = 4); both store 16
+// bytes per lane and row.  Points are normalised in FP64 either way.
+template <typename TIO, int PPL>
+__global__ __launch_bounds__(kRecBlock) void rec_kernel(const TIO* __restrict__ xyz, TIO* __restrict__ out,
                                                         uint32_t n, int64_t ld, int lmax)
 {
-    using V = std::conditional_t<PPL == 1, double, double2_t>;
+    using V = typename vec_of<TIO, PPL>::type;
     const uint32_t i0 = (xcd_tile(blockIdx.x, gridDim.x) * kRecBlock + threadIdx.x) * PPL;
     if (i0 >= n) return;
     V x, y, z, k;
-#pragma unroll
-    for (int q = 0; q < PPL; ++q) {
-        const double* p = xyz + 3 * size_t(i0 + q);
-        double xb, yb, zb, kb;
-        normalize(p[0], p[1], p[2], xb, yb, zb, kb);
-        if constexpr (PPL == 1) {
-            x = xb, y = yb, z = zb, k = kb;
-        } else {
-            x[q] = xb, y[q] = yb, z[q] = zb, k[q] = kb;
-        }
-    }
-    const uint32_t boff = i0 * uint32_t(sizeof(double));
+    load_points<TIO, PPL>(xyz, nullptr, In::kXyz, i0, x, y, z, k);
+    const uint32_t boff = i0 * uint32_t(sizeof(TIO));
     eval_unit_rec<V>(x, y, z, k, lmax, [&](int r, V v) {
         *reinterpret_cast<V*>(reinterpret_cast<char*>(out + int64_t(r) * ld) + boff) = v;
     });
 }
 
-template <int PPL>
-static hipError_t launch_rec_one(int lmax, int64_t n, const double* xyz, double* out, int64_t ld, hipStream_t s)
+template <typename TIO, int PPL>
+static hipError_t launch_rec_one(int lmax, int64_t n, const TIO* xyz, TIO* out, int64_t ld, hipStream_t s)
 {
     const unsigned grid = unsigned((n / PPL + kRecBlock - 1) / kRecBlock);
-    hipLaunchKernelGGL((rec_kernel<PPL>), dim3(grid), dim3(kRecBlock), PPL > 1 ? kRecCapLds : 0, s, xyz, out,
+    hipLaunchKernelGGL((rec_kernel<TIO, PPL>), dim3(grid), dim3(kRecBlock), PPL > 1 ? kRecCapLds : 0, s, xyz, out,
                        uint32_t(n), ld, lmax);
     return hipGetLastError();
 }
 
-hipError_t launch_rec(int lmax, int64_t n, const double* xyz, double* out, int64_t ld, hipStream_t s)
+template <typename TIO>
+hipError_t launch_rec(int lmax, int64_t n, const TIO* xyz, TIO* out, int64_t ld, hipStream_t s)
 {
-    const bool vec_ok = ld % 2 == 0 && reinterpret_cast<uintptr_t>(out) % 16 == 0;
+    constexpr int kVec = 16 / sizeof(TIO);
+    const bool vec_ok = ld % kVec == 0 && reinterpret_cast<uintptr_t>(out) % 16 == 0;
     for (int64_t c0 = 0; c0 < n; c0 += kRecChunk) {
         const int64_t nc = n - c0 < kRecChunk ? n - c0 : kRecChunk;
-        const int64_t nmain = vec_ok ? nc - nc % 2 : 0;
+        const int64_t nmain = vec_ok ? nc - nc % kVec : 0;
         hipError_t e = hipSuccess;
-        if (nmain) e = launch_rec_one<2>(lmax, nmain, xyz + 3 * c0, out + c0, ld, s);
+        if (nmain) e = launch_rec_one<TIO, kVec>(lmax, nmain, xyz + 3 * c0, out + c0, ld, s);
         if (e == hipSuccess && nmain < nc)
-            e = launch_rec_one<1>(lmax, nc - nmain, xyz + 3 * (c0 + nmain), out + c0 + nmain, ld, s);
+            e = launch_rec_one<TIO, 1>(lmax, nc - nmain, xyz + 3 * (c0 + nmain), out + c0 + nmain, ld, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
+
+template hipError_t launch_rec<double>(int, int64_t, const double*, double*, int64_t, hipStream_t);
+template hipError_t launch_rec<float>(int, int64_t, const float*, float*, int64_t, hipStream_t);
 
 }  // namespace shk

@@ -137,3 +137,11 @@ extern "C" void core_spline4(int n_tables, int n_r, double r_max, const double *
         for (int l = 0; l < 4; ++l) out[4 * k + l] = R[l];
     }
 }
+
+// FP32 recurrence core at float unit vectors: out[(lmax+1)^2][n].
+extern "C" void core_rec_f32(long n, const float *u, int lmax, float *out)
+{
+    for (long i = 0; i < n; ++i)
+        shk::eval_unit_rec<float>(u[3 * i], u[3 * i + 1], u[3 * i + 2], 1.0f, lmax,
+                                  [&](int r, float v) { out[r * n + i] = v; });
+}

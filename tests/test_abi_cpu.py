@@ -112,6 +112,9 @@ def test_interface_variants_validation(L):
     assert L.sh_eval_rec(-1, 5, fake, fake, None) == 1
     assert L.sh_eval_rec(24, 5, None, fake, None) == 1
     assert L.sh_eval_rec(24, 0, None, None, None) == 0
+    assert L.sh_eval_rec_f32(25, 5, fake, fake, None) == 1
+    assert L.sh_eval_rec_f32(24, 5, fake, None, None) == 1
+    assert L.sh_eval_rec_f32(24, 0, None, None, None) == 0
     for fn in ("sh_eval_angles", "sh_eval_angles_f32"):
         assert getattr(L, fn)(10, 5, fake, fake, fake, None) == 1
         assert getattr(L, fn)(3, 5, fake, None, fake, None) == 1
@@ -133,3 +136,6 @@ def test_rec_validation(L):
     assert L.sh_eval_rec(-1, 5, fake, fake, None) == 1
     assert L.sh_eval_rec(24, 5, None, fake, None) == 1
     assert L.sh_eval_rec(24, 0, None, None, None) == 0
+    assert L.sh_eval_rec_f32(25, 5, fake, fake, None) == 1
+    assert L.sh_eval_rec_f32(24, 5, fake, None, None) == 1
+    assert L.sh_eval_rec_f32(24, 0, None, None, None) == 0

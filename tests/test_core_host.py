@@ -172,3 +172,17 @@ def test_core_spline_interleaved_tables(core, orc):
             M = orc.spline_setup(y[t, l], r_max)
             ref = orc.spline_eval(y[t, l], M, r_max, r)
             assert np.abs(out[:, l].astype(LD) - ref).max() <= 1e-13, (t, l)
+
+
+@pytest.mark.parametrize("lmax", [9, 24])
+def test_core_recurrence_fp32(core, orc, lmax):
+    """FP32 recurrence core at float unit vectors: per-l error <= 5e-6 up to l = 9
+    and 1e-6 (l + 1) beyond, against the oracle at the same float vectors."""
+    core.core_rec_f32.argtypes = [ctypes.c_long, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]
+    u = _units(_pts()[:20000], np.float32)
+    F = (lmax + 1) ** 2
+    out = np.empty((F, u.shape[0]), dtype=np.float32)
+    core.core_rec_f32(u.shape[0], u.ctypes.data, lmax, out.ctypes.data)
+    err = np.abs(out.astype(LD) - orc.eval_xyz(lmax, u)).max(axis=1)
+    for l in range(lmax + 1):
+        assert err[l * l:(l + 1) * (l + 1)].max() <= (5e-6 if l <= 9 else 1e-6 * (l + 1)), l

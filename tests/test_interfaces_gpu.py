@@ -134,3 +134,20 @@ def test_complex_and_spinor_other_inputs(dev, orc, dtype):
         gs = sh.sh_eval_spinor_angles(9, torch.from_numpy(th).to(dev), torch.from_numpy(ph).to(dev)).cpu().numpy()
         assert np.abs(gs.real.astype(LD) - sre).max() <= tol
         assert np.abs(gs.imag.astype(LD) - sim).max() <= tol
+
+
+@pytest.mark.parametrize("lmax", [0, 9, 16, 24])
+@pytest.mark.parametrize("n_random", [20000, 19998])
+def test_recurrence_fp32(dev, orc, lmax, n_random):
+    """FP32 recurrence (four points per lane; 20064 and 20062 points leave remainders
+    of 0 and 2): max abs error per l <= 5e-6 for l <= 9 and 1e-6 (l + 1) beyond,
+    against the oracle at the float inputs."""
+    pts = workloads.points_plain_eval(seed=5, n_random=n_random).astype(np.float32)
+    got = sh.sh_eval_rec_f32(lmax, torch.from_numpy(pts).to(dev)).cpu().numpy()
+    err = np.abs(got.astype(LD) - orc.eval_xyz(lmax, pts)).max(axis=1)
+    for l in range(lmax + 1):
+        tol = 5e-6 if l <= 9 else 1e-6 * (l + 1)
+        assert err[l * l:(l + 1) * (l + 1)].max() <= tol, (l, err[l * l:(l + 1) * (l + 1)].max())
+    if lmax <= 9:  # the explicit FP32 formulas agree within both bounds
+        ex = sh.sh_eval_f32(lmax, torch.from_numpy(pts).to(dev)).cpu().numpy()
+        assert np.abs(got - ex).max() <= 1e-5
