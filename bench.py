@@ -236,6 +236,14 @@ def bench_interfaces(sh, xyz, out, steps):
     b = nr * (24 + 289 * 8)
     res["rec_l16"] = {"n_points": nr, "points_per_s": nr / avg, "kernel_ms": avg * 1e3, "gbs": b / avg / 1e9,
                       "frac": b / avg / 1e9 / HBM_PEAK_GBS, "bytes_per_point": 24 + 289 * 8}
+    orr32 = out.view(-1)[: 289 * nr // 2].view(torch.float32).view(289, nr)
+    xr32 = xr.to(torch.float32)
+    _, per = time_launches(lambda: sh.sh_eval_rec_f32(16, xr32, out=orr32), steps, 2)
+    avg = sum(per) / len(per)
+    b = nr * (12 + 289 * 4)
+    res["rec_l16_f32"] = {"n_points": nr, "points_per_s": nr / avg, "kernel_ms": avg * 1e3, "gbs": b / avg / 1e9,
+                          "frac": b / avg / 1e9 / HBM_PEAK_GBS, "bytes_per_point": 12 + 289 * 4}
+    del xr32
     return res
 
 
