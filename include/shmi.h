@@ -99,6 +99,15 @@ int sh_eval_rec(int lmax, int64_t n, const double *xyz, double *out, hipStream_t
  * 1e-6 (l + 1) beyond (the recurrence accumulates rounding with l). */
 int sh_eval_rec_f32(int lmax, int64_t n, const float *xyz, float *out, hipStream_t stream);
 
+/* Complex and spinor harmonics for 0 <= lmax <= SH_LMAX_REC, built from the
+ * recurrence's real harmonics exactly as sh_eval_complex_in and sh_eval_spinor_in
+ * build them from the explicit ones (same arguments, input interfaces and output
+ * layout).  Error bounds as sh_eval_rec (FP64) and sh_eval_rec_f32 (FP32). */
+int sh_eval_complex_rec(int lmax, int64_t n, int input, int dtype, const void *in0, const void *in1, void *out,
+                        hipStream_t stream);
+int sh_eval_spinor_rec(int lmax, int64_t n, int input, int dtype, const void *in0, const void *in1, void *out,
+                       hipStream_t stream);
+
 /* Complex harmonics Y_l^m (eq. sphericalfromlegendre, with the Condon-Shortley
  * phase), built from the real ones (Section 3): Y_l^0 = R_l^0 and, for m > 0,
  *   Y_l^m = (-1)^m (R_l^m + i R_l^-m) / sqrt(2),   Y_l^-m = (R_l^m - i R_l^-m) / sqrt(2)

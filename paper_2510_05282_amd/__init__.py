@@ -24,7 +24,7 @@ __all__ = ["SH_F32", "SH_F64", "SH_LMAX", "SH_LMAX_REC", "Radial", "ShError", "S
            "sh_eval_angles", "sh_eval_angles_f32", "sh_eval_complex", "sh_eval_complex_f32",
            "sh_eval_spinor", "sh_eval_spinor_f32", "spinor_index", "sh_eval_complex_unit",
            "sh_eval_complex_angles", "sh_eval_spinor_unit", "sh_eval_spinor_angles",
-           "SH_IN_XYZ", "SH_IN_UNIT", "SH_IN_ANGLES",
+           "SH_IN_XYZ", "SH_IN_UNIT", "SH_IN_ANGLES", "sh_eval_complex_rec", "sh_eval_spinor_rec",
            "sh_eval_f32", "sh_eval_grad", "sh_eval_grad_f32", "sh_eval_jac", "sh_eval_ld",
            "sh_eval_rec", "sh_eval_rec_f32", "sh_eval_unit", "sh_eval_unit_f32",
            "sh_projectors", "sh_projectors_f32", "sh_radial_create", "sh_radial_destroy",
@@ -232,6 +232,19 @@ def _cplx_in(fn: str, spinor: bool, lmax: int, input_kind: int, a: torch.Tensor,
                                      b.data_ptr() if input_kind == SH_IN_ANGLES else None, out.data_ptr(),
                                      _stream(a.device, stream)))
     return out
+
+
+def sh_eval_complex_rec(lmax: int, a: torch.Tensor, b: torch.Tensor | None = None, input_kind: int = SH_IN_XYZ,
+                        out=None, stream=None) -> torch.Tensor:
+    """Complex harmonics for lmax <= 24 by recurrence; a = xyz or unit vectors [n, 3],
+    or a = theta and b = phi with input_kind = SH_IN_ANGLES."""
+    return _cplx_in("sh_eval_complex_rec", False, lmax, input_kind, a, b, out, stream)
+
+
+def sh_eval_spinor_rec(lmax: int, a: torch.Tensor, b: torch.Tensor | None = None, input_kind: int = SH_IN_XYZ,
+                       out=None, stream=None) -> torch.Tensor:
+    """Spinor harmonics for lmax <= 24 by recurrence; inputs as sh_eval_complex_rec."""
+    return _cplx_in("sh_eval_spinor_rec", True, lmax, input_kind, a, b, out, stream)
 
 
 def sh_eval_complex_unit(lmax: int, u: torch.Tensor, out=None, stream=None) -> torch.Tensor:

@@ -57,7 +57,7 @@ def lib() -> ctypes.CDLL:
                "sh_eval_spinor", "sh_eval_spinor_f32"):
         getattr(L, fn).argtypes = [i32, i64, vp, vp, vp]
         getattr(L, fn).restype = i32
-    for fn in ("sh_eval_complex_in", "sh_eval_spinor_in"):
+    for fn in ("sh_eval_complex_in", "sh_eval_spinor_in", "sh_eval_complex_rec", "sh_eval_spinor_rec"):
         getattr(L, fn).argtypes = [i32, i64, i32, i32, vp, vp, vp, vp]
         getattr(L, fn).restype = i32
     for fn in ("sh_eval_angles", "sh_eval_angles_f32"):

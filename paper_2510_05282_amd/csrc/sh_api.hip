@@ -33,28 +33,33 @@ static_assert(int(shk::In::kXyz) == SH_IN_XYZ && int(shk::In::kUnit) == SH_IN_UN
                   int(shk::In::kAngles) == SH_IN_ANGLES,
               "the kernels' input kinds and sh_input must agree");
 
-// Complex (SPINOR = false) or spinor harmonics from any input interface.
-template <bool SPINOR, typename TIO>
+// Complex (SPINOR = false) or spinor harmonics from any input interface, by the
+// explicit formulas (REC = false, lmax <= SH_LMAX) or the recurrence (REC = true,
+// lmax <= SH_LMAX_REC).
+template <bool SPINOR, bool REC, typename TIO>
 static int eval_cplx(int lmax, int64_t n, int input, const TIO *in0, const TIO *in1, TIO *out, hipStream_t stream)
 {
-    if (bad_lmax(lmax) || n < 0) return SH_EINVAL;
+    if (lmax < 0 || lmax > (REC ? SH_LMAX_REC : SH_LMAX) || n < 0) return SH_EINVAL;
     if (input != SH_IN_XYZ && input != SH_IN_UNIT && input != SH_IN_ANGLES) return SH_EINVAL;
     if (n == 0) return SH_OK;
     if (!in0 || !out || (input == SH_IN_ANGLES && !in1)) return SH_EINVAL;
+    if (REC)
+        return hip_status(SPINOR ? shk::launch_rec_spinor<TIO>(lmax, n, input, in0, in1, out, n, stream)
+                                 : shk::launch_rec_complex<TIO>(lmax, n, input, in0, in1, out, n, stream));
     return hip_status(SPINOR ? shk::launch_fwd_spinor<TIO>(lmax, n, input, in0, in1, out, n, stream)
                              : shk::launch_fwd_complex<TIO>(lmax, n, input, in0, in1, out, n, stream));
 }
 
-template <bool SPINOR>
+template <bool SPINOR, bool REC>
 static int eval_cplx_any(int lmax, int64_t n, int input, int dtype, const void *in0, const void *in1, void *out,
                          hipStream_t stream)
 {
     if (dtype == SH_F64)
-        return eval_cplx<SPINOR, double>(lmax, n, input, static_cast<const double *>(in0),
-                                         static_cast<const double *>(in1), static_cast<double *>(out), stream);
+        return eval_cplx<SPINOR, REC, double>(lmax, n, input, static_cast<const double *>(in0),
+                                              static_cast<const double *>(in1), static_cast<double *>(out), stream);
     if (dtype == SH_F32)
-        return eval_cplx<SPINOR, float>(lmax, n, input, static_cast<const float *>(in0),
-                                        static_cast<const float *>(in1), static_cast<float *>(out), stream);
+        return eval_cplx<SPINOR, REC, float>(lmax, n, input, static_cast<const float *>(in0),
+                                             static_cast<const float *>(in1), static_cast<float *>(out), stream);
     return SH_EINVAL;
 }
 
@@ -143,34 +148,46 @@ int sh_eval_angles_f32(int lmax, int64_t n, const float *theta, const float *phi
 
 int sh_eval_complex(int lmax, int64_t n, const double *xyz, double *out, hipStream_t stream)
 {
-    return eval_cplx<false, double>(lmax, n, SH_IN_XYZ, xyz, nullptr, out, stream);
+    return eval_cplx<false, false, double>(lmax, n, SH_IN_XYZ, xyz, nullptr, out, stream);
 }
 
 int sh_eval_complex_f32(int lmax, int64_t n, const float *xyz, float *out, hipStream_t stream)
 {
-    return eval_cplx<false, float>(lmax, n, SH_IN_XYZ, xyz, nullptr, out, stream);
+    return eval_cplx<false, false, float>(lmax, n, SH_IN_XYZ, xyz, nullptr, out, stream);
 }
 
 int sh_eval_complex_in(int lmax, int64_t n, int input, int dtype, const void *in0, const void *in1, void *out,
                        hipStream_t stream)
 {
-    return eval_cplx_any<false>(lmax, n, input, dtype, in0, in1, out, stream);
+    return eval_cplx_any<false, false>(lmax, n, input, dtype, in0, in1, out, stream);
 }
 
 int sh_eval_spinor(int lmax, int64_t n, const double *xyz, double *out, hipStream_t stream)
 {
-    return eval_cplx<true, double>(lmax, n, SH_IN_XYZ, xyz, nullptr, out, stream);
+    return eval_cplx<true, false, double>(lmax, n, SH_IN_XYZ, xyz, nullptr, out, stream);
 }
 
 int sh_eval_spinor_f32(int lmax, int64_t n, const float *xyz, float *out, hipStream_t stream)
 {
-    return eval_cplx<true, float>(lmax, n, SH_IN_XYZ, xyz, nullptr, out, stream);
+    return eval_cplx<true, false, float>(lmax, n, SH_IN_XYZ, xyz, nullptr, out, stream);
 }
 
 int sh_eval_spinor_in(int lmax, int64_t n, int input, int dtype, const void *in0, const void *in1, void *out,
                       hipStream_t stream)
 {
-    return eval_cplx_any<true>(lmax, n, input, dtype, in0, in1, out, stream);
+    return eval_cplx_any<true, false>(lmax, n, input, dtype, in0, in1, out, stream);
+}
+
+int sh_eval_complex_rec(int lmax, int64_t n, int input, int dtype, const void *in0, const void *in1, void *out,
+                        hipStream_t stream)
+{
+    return eval_cplx_any<false, true>(lmax, n, input, dtype, in0, in1, out, stream);
+}
+
+int sh_eval_spinor_rec(int lmax, int64_t n, int input, int dtype, const void *in0, const void *in1, void *out,
+                       hipStream_t stream)
+{
+    return eval_cplx_any<true, true>(lmax, n, input, dtype, in0, in1, out, stream);
 }
 
 int sh_eval_rec(int lmax, int64_t n, const double *xyz, double *out, hipStream_t stream)

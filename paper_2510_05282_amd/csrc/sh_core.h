@@ -196,32 +196,43 @@ __host__ __device__ __forceinline__ void complex_unit(T x, T y, T z, T keep, Sin
 // components with fixed coefficients and is passed on as soon as it is formed.
 // Spinor index k (l-major; j = l - 1/2 first; m_j ascending):
 //     j = l - 1/2: k = 2l^2 + (m_j + l - 1/2),   j = l + 1/2: k = 2l^2 + 2l + (m_j + l + 1/2).
-// sink(k, c, re, im) receives component c (0 = upper) of spinor k; every (k, c)
-// of l <= LMAX is delivered exactly once, the structural zeros included.
+// spinor_spread passes the components fed by one Y_l^m = re + i im to
+// sink(k, c, re, im) (c = 0 for the upper component); coef(l, q) = sqrt(q/(2l+1)).
+// Over all m of an l, every (k, c) of that l is delivered exactly once, the
+// structural zeros included.
+template <typename T, typename Coef, typename Sink>
+__host__ __device__ __forceinline__ void spinor_spread(int l, int m, T re, T im, Coef&& coef, Sink&& sink)
+{
+    using S = scalar_t<T>;
+    const int base = 2 * l * l;
+    // j = l + 1/2: upper of m_j = m + 1/2, lower of m_j = m - 1/2
+    const T cu = T(S(coef(l, l + m + 1))), cl = T(S(coef(l, l - m + 1)));
+    sink(base + 3 * l + m + 1, 0, cu * re, cu * im);
+    sink(base + 3 * l + m, 1, cl * re, cl * im);
+    if (m <= l - 1) {  // j = l - 1/2, upper of m_j = m + 1/2
+        const T c = T(S(-coef(l, l - m)));
+        sink(base + l + m, 0, c * re, c * im);
+    }
+    if (m >= 1 - l) {  // j = l - 1/2, lower of m_j = m - 1/2
+        const T c = T(S(coef(l, l + m)));
+        sink(base + l + m - 1, 1, c * re, c * im);
+    }
+    const T zero = T(S(0));
+    if (m == l) sink(base + 4 * l + 1, 1, zero, zero);  // j = l + 1/2, m_j = l + 1/2
+    if (m == -l) sink(base + 2 * l, 0, zero, zero);     // j = l + 1/2, m_j = -l - 1/2
+}
+
+// sqrt(q / (2l + 1)) for the explicit kernels, whose (l, q) are compile-time
+// constants after unrolling, so the square root folds away.
+struct SpinorCoef {
+    __host__ __device__ double operator()(int l, int q) const { return sqrt(double(q) / double(2 * l + 1)); }
+};
+
 template <int LMAX, typename T, typename Sink>
 __host__ __device__ __forceinline__ void spinor_unit(T x, T y, T z, T keep, Sink&& sink)
 {
-    using S = scalar_t<T>;
-    complex_unit<LMAX, T>(x, y, z, keep, [&](int l, int m, T re, T im) {
-        const S inv = S(1) / S(2 * l + 1);
-        const int base = 2 * l * l;
-        // j = l + 1/2: upper of m_j = m + 1/2, lower of m_j = m - 1/2
-        const T cu = T(S(sqrt(double(l + m + 1) * double(inv))));
-        const T cl = T(S(sqrt(double(l - m + 1) * double(inv))));
-        sink(base + 2 * l + l + m + 1, 0, cu * re, cu * im);
-        sink(base + 2 * l + l + m, 1, cl * re, cl * im);
-        if (m <= l - 1) {  // j = l - 1/2, upper of m_j = m + 1/2
-            const T c = T(S(-sqrt(double(l - m) * double(inv))));
-            sink(base + l + m, 0, c * re, c * im);
-        }
-        if (m >= 1 - l) {  // j = l - 1/2, lower of m_j = m - 1/2
-            const T c = T(S(sqrt(double(l + m) * double(inv))));
-            sink(base + l + m - 1, 1, c * re, c * im);
-        }
-        const T zero = T(S(0));
-        if (m == l) sink(base + 4 * l + 1, 1, zero, zero);  // j = l + 1/2, m_j = l + 1/2
-        if (m == -l) sink(base + 2 * l, 0, zero, zero);     // j = l + 1/2, m_j = -l - 1/2
-    });
+    complex_unit<LMAX, T>(x, y, z, keep,
+                          [&](int l, int m, T re, T im) { spinor_spread(l, m, re, im, SpinorCoef{}, sink); });
 }
 
 // 1/sqrt(a) for a > 0: the hardware estimate (v_rsq_f64) refined by two Newton

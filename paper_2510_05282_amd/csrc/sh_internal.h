@@ -44,6 +44,14 @@ hipError_t launch_fwd_spinor(int lmax, int64_t n, int input, const TIO* in0, con
 // Real harmonics up to lmax <= SH_LMAX_REC by recurrence.
 template <typename TIO>
 hipError_t launch_rec(int lmax, int64_t n, const TIO* xyz, TIO* out, int64_t ld, hipStream_t s);
+// Complex and spinor harmonics by recurrence (lmax <= SH_LMAX_REC), inputs and
+// layout as launch_fwd_complex / launch_fwd_spinor.
+template <typename TIO>
+hipError_t launch_rec_complex(int lmax, int64_t n, int input, const TIO* in0, const TIO* in1, TIO* out, int64_t ld,
+                              hipStream_t s);
+template <typename TIO>
+hipError_t launch_rec_spinor(int lmax, int64_t n, int input, const TIO* in0, const TIO* in1, TIO* out, int64_t ld,
+                             hipStream_t s);
 
 // Values out[F][ld] and Jacobian jac[3][F][ld] in one pass (FP64).
 hipError_t launch_jac(int lmax, int64_t n, const double* xyz, double* out, double* jac, int64_t ld, hipStream_t s);

@@ -10,7 +10,8 @@
 
 namespace shk {
 
-// All (lmax+1)^2 values at the unit vector (x, y, z); store(row, value).  keep
+// All (lmax+1)^2 values at the unit vector (x, y, z); store(l, m, value), and for
+// m > 0 the value of +m comes just before that of -m.  keep
 // masks the m = 0 rows of l > 0 at the origin, as in eval_unit.  T is double or a
 // clang vector of doubles (that many points at once).  The loops run over the
 // runtime lmax; every coefficient is a table entry indexed by (l, m) alone, so
@@ -41,15 +42,48 @@ __host__ __device__ __forceinline__ void eval_unit_rec(T x, T y, T z, T keep, in
                 y2 = y1;
                 y1 = yl;
             }
-            const int r0 = l * l + l;
             if (m == 0) {
-                store(r0, l > 0 ? yl * keep : yl);
+                store(l, 0, l > 0 ? yl * keep : yl);
             } else {
-                store(r0 + m, yl * c);
-                store(r0 - m, yl * s);
+                store(l, m, yl * c);
+                store(l, -m, yl * s);
             }
         }
     }
+}
+
+// Complex harmonics (Condon-Shortley phase) from the recurrence's real values, as
+// complex_unit does for the explicit ones: Y_l^0 = R_l^0, and for m > 0
+//     Y_l^m = (-1)^m (R_l^m + i R_l^-m) / sqrt(2),   Y_l^-m = (R_l^m - i R_l^-m) / sqrt(2);
+// sink(l, m, re, im).
+template <typename T, typename Sink>
+__host__ __device__ __forceinline__ void complex_unit_rec(T x, T y, T z, T keep, int lmax, Sink&& sink)
+{
+    using S = scalar_t<T>;
+    const T h = T(S(0.70710678118654752440));  // 1/sqrt(2)
+    T cos_part = T(S(0));
+    eval_unit_rec<T>(x, y, z, keep, lmax, [&](int l, int m, T v) {
+        if (m == 0) {
+            sink(l, 0, v, T(S(0)));
+        } else if (m > 0) {
+            cos_part = v;  // R_l^m arrives just before R_l^-m
+        } else {
+            const T re = h * cos_part, im = h * v;
+            if (-m & 1) sink(l, -m, -re, -im);
+            else sink(l, -m, re, im);
+            sink(l, m, re, -im);
+        }
+    });
+}
+
+// Spinor harmonics (eq. spinorial) from complex_unit_rec, with the coefficient
+// table of sh_rec_constants.h; sink(k, c, re, im) as for spinor_unit.
+template <typename T, typename Sink>
+__host__ __device__ __forceinline__ void spinor_unit_rec(T x, T y, T z, T keep, int lmax, Sink&& sink)
+{
+    complex_unit_rec<T>(x, y, z, keep, lmax, [&](int l, int m, T re, T im) {
+        spinor_spread(l, m, re, im, [](int ll, int q) { return shc::kSpinP[ll][q]; }, sink);
+    });
 }
 
 }  // namespace shk

@@ -49,8 +49,8 @@ __global__ __launch_bounds__(kRecBlock) void rec_kernel(const TIO* __restrict__ 
     V x, y, z, k;
     load_points<TIO, PPL>(xyz, nullptr, In::kXyz, i0, x, y, z, k);
     const uint32_t boff = i0 * uint32_t(sizeof(TIO));
-    eval_unit_rec<V>(x, y, z, k, lmax, [&](int r, V v) {
-        *reinterpret_cast<V*>(reinterpret_cast<char*>(out + int64_t(r) * ld) + boff) = v;
+    eval_unit_rec<V>(x, y, z, k, lmax, [&](int l, int m, V v) {
+        *reinterpret_cast<V*>(reinterpret_cast<char*>(out + int64_t(row(l, m)) * ld) + boff) = v;
     });
 }
 
@@ -82,5 +82,85 @@ hipError_t launch_rec(int lmax, int64_t n, const TIO* xyz, TIO* out, int64_t ld,
 
 template hipError_t launch_rec<double>(int, int64_t, const double*, double*, int64_t, hipStream_t);
 template hipError_t launch_rec<float>(int, int64_t, const float*, float*, int64_t, hipStream_t);
+
+// Complex (SPINOR = false) or spinor harmonics by recurrence, any input interface:
+// the lanes and layout of fwd_complex_kernel / fwd_spinor_kernel, lmax at run time.
+template <typename TIO, int PPL, bool SPINOR>
+__global__ __launch_bounds__(kRecBlock) void rec_cplx_kernel(const TIO* __restrict__ in0, TIO* __restrict__ out,
+                                                             uint32_t n, int64_t ld, const TIO* __restrict__ in1,
+                                                             In mode, int lmax)
+{
+    using V = typename vec_of<TIO, PPL>::type;
+    using W = typename vec_of<TIO, 2 * PPL>::type;
+    const uint32_t i0 = (xcd_tile(blockIdx.x, gridDim.x) * kRecBlock + threadIdx.x) * PPL;
+    if (i0 >= n) return;
+    V x, y, z, k;
+    load_points<TIO, PPL>(in0, in1, mode, i0, x, y, z, k);
+    const uint32_t boff = i0 * uint32_t(2 * sizeof(TIO));
+    auto put = [&](int64_t r, V re, V im) {
+        *reinterpret_cast<W*>(reinterpret_cast<char*>(out + 2 * r * ld) + boff) = interleave<TIO, PPL>(re, im);
+    };
+    if constexpr (SPINOR)
+        spinor_unit_rec<V>(x, y, z, k, lmax, [&](int s, int c, V re, V im) { put(2 * s + c, re, im); });
+    else
+        complex_unit_rec<V>(x, y, z, k, lmax, [&](int l, int m, V re, V im) { put(row(l, m), re, im); });
+}
+
+template <typename TIO, int PPL, bool SPINOR>
+static hipError_t launch_rec_cplx_one(int lmax, int64_t n, In mode, const TIO* a, const TIO* b, TIO* out,
+                                      int64_t ld, hipStream_t s)
+{
+    const unsigned grid = unsigned((n / PPL + kRecBlock - 1) / kRecBlock);
+    const size_t lds = PPL * sizeof(TIO) * 2 == 16 ? kRecCapLds : 0;
+    hipLaunchKernelGGL((rec_cplx_kernel<TIO, PPL, SPINOR>), dim3(grid), dim3(kRecBlock), lds, s, a, out,
+                       uint32_t(n), ld, b, mode, lmax);
+    return hipGetLastError();
+}
+
+template <typename TIO, bool SPINOR>
+static hipError_t launch_rec_cplx(int lmax, int64_t n, int input, const TIO* in0, const TIO* in1, TIO* out,
+                                  int64_t ld, hipStream_t s)
+{
+    constexpr int kVec = sizeof(TIO) == 4 ? 2 : 1;
+    const In mode = In(input);
+    const int64_t stride = mode == In::kAngles ? 1 : 3;
+    const bool vec_ok = ld % kVec == 0 && reinterpret_cast<uintptr_t>(out) % 16 == 0;
+    for (int64_t c0 = 0; c0 < n; c0 += kRecChunk) {
+        const int64_t nc = n - c0 < kRecChunk ? n - c0 : kRecChunk;
+        const int64_t nmain = vec_ok ? nc - nc % kVec : 0;
+        auto a = [&](int64_t c) { return in0 + stride * c; };
+        auto b = [&](int64_t c) { return mode == In::kAngles ? in1 + c : in1; };
+        hipError_t e = hipSuccess;
+        if (nmain) e = launch_rec_cplx_one<TIO, kVec, SPINOR>(lmax, nmain, mode, a(c0), b(c0), out + 2 * c0, ld, s);
+        if (e == hipSuccess && nmain < nc)
+            e = launch_rec_cplx_one<TIO, 1, SPINOR>(lmax, nc - nmain, mode, a(c0 + nmain), b(c0 + nmain),
+                                                    out + 2 * (c0 + nmain), ld, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <typename TIO>
+hipError_t launch_rec_complex(int lmax, int64_t n, int input, const TIO* in0, const TIO* in1, TIO* out, int64_t ld,
+                              hipStream_t s)
+{
+    return launch_rec_cplx<TIO, false>(lmax, n, input, in0, in1, out, ld, s);
+}
+
+template <typename TIO>
+hipError_t launch_rec_spinor(int lmax, int64_t n, int input, const TIO* in0, const TIO* in1, TIO* out, int64_t ld,
+                             hipStream_t s)
+{
+    return launch_rec_cplx<TIO, true>(lmax, n, input, in0, in1, out, ld, s);
+}
+
+template hipError_t launch_rec_complex<double>(int, int64_t, int, const double*, const double*, double*, int64_t,
+                                               hipStream_t);
+template hipError_t launch_rec_complex<float>(int, int64_t, int, const float*, const float*, float*, int64_t,
+                                              hipStream_t);
+template hipError_t launch_rec_spinor<double>(int, int64_t, int, const double*, const double*, double*, int64_t,
+                                              hipStream_t);
+template hipError_t launch_rec_spinor<float>(int, int64_t, int, const float*, const float*, float*, int64_t,
+                                             hipStream_t);
 
 }  // namespace shk

@@ -74,7 +74,7 @@ extern "C" void core_rec(long n, const double *u, int lmax, double *out)
 {
     for (long i = 0; i < n; ++i)
         shk::eval_unit_rec<double>(u[3 * i], u[3 * i + 1], u[3 * i + 2], 1.0, lmax,
-                           [&](int r, double v) { out[r * n + i] = v; });
+                                   [&](int l, int m, double v) { out[shk::row(l, m) * n + i] = v; });
 }
 
 // Complex and spinor cores at unit vectors: (re, im) pairs, out[rows][n][2] with
@@ -143,5 +143,30 @@ extern "C" void core_rec_f32(long n, const float *u, int lmax, float *out)
 {
     for (long i = 0; i < n; ++i)
         shk::eval_unit_rec<float>(u[3 * i], u[3 * i + 1], u[3 * i + 2], 1.0f, lmax,
-                                  [&](int r, float v) { out[r * n + i] = v; });
+                                  [&](int l, int m, float v) { out[shk::row(l, m) * n + i] = v; });
+}
+
+// Complex and spinor harmonics by recurrence at unit vectors (any lmax <= 24):
+// complex out[F][n][2]; spinor out[S][2][n][2] with a write count per entry.
+extern "C" void core_complex_rec(long n, const double *u, int lmax, double *out)
+{
+    for (long i = 0; i < n; ++i)
+        shk::complex_unit_rec<double>(u[3 * i], u[3 * i + 1], u[3 * i + 2], 1.0, lmax,
+                                      [&](int l, int m, double re, double im) {
+                                          double *o = out + 2 * (long(shk::row(l, m)) * n + i);
+                                          o[0] = re;
+                                          o[1] = im;
+                                      });
+}
+
+extern "C" void core_spinor_rec(long n, const double *u, int lmax, double *out, int *count)
+{
+    for (long i = 0; i < n; ++i)
+        shk::spinor_unit_rec<double>(u[3 * i], u[3 * i + 1], u[3 * i + 2], 1.0, lmax,
+                                     [&](int k, int c, double re, double im) {
+                                         const long e = long(2 * k + c) * n + i;
+                                         out[2 * e] = re;
+                                         out[2 * e + 1] = im;
+                                         count[e] += 1;
+                                     });
 }

@@ -100,12 +100,16 @@ def test_interface_variants_validation(L):
         assert getattr(L, fn)(10, 5, fake, fake, None) == 1
         assert getattr(L, fn)(3, 5, None, fake, None) == 1
         assert getattr(L, fn)(3, 0, None, None, None) == 0
-    for fn in ("sh_eval_complex_in", "sh_eval_spinor_in"):
+    assert L.sh_eval_complex_rec(24, 0, 2, 0, None, None, None, None) == 0
+    assert L.sh_eval_complex_rec(25, 5, 0, 0, fake, None, fake, None) == 1
+    assert L.sh_eval_spinor_rec(25, 5, 0, 1, fake, None, fake, None) == 1
+    assert L.sh_eval_complex_in(10, 5, 0, 0, fake, None, fake, None) == 1  # explicit forms stop at 9
+    for fn in ("sh_eval_complex_in", "sh_eval_spinor_in", "sh_eval_complex_rec", "sh_eval_spinor_rec"):
         f = getattr(L, fn)
         assert f(3, 5, 3, 0, fake, fake, fake, None) == 1     # unknown input kind
         assert f(3, 5, 0, 2, fake, fake, fake, None) == 1     # unknown dtype
         assert f(3, 5, 2, 0, fake, None, fake, None) == 1     # angles need phi
-        assert f(10, 5, 1, 1, fake, None, fake, None) == 1    # lmax
+        assert f(25 if fn.endswith("_rec") else 10, 5, 1, 1, fake, None, fake, None) == 1  # lmax
         assert f(3, 5, 1, 0, None, None, fake, None) == 1
         assert f(3, 0, 2, 1, None, None, None, None) == 0     # n == 0
     assert L.sh_eval_rec(25, 5, fake, fake, None) == 1  # beyond SH_LMAX_REC

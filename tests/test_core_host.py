@@ -186,3 +186,27 @@ def test_core_recurrence_fp32(core, orc, lmax):
     err = np.abs(out.astype(LD) - orc.eval_xyz(lmax, u)).max(axis=1)
     for l in range(lmax + 1):
         assert err[l * l:(l + 1) * (l + 1)].max() <= (5e-6 if l <= 9 else 1e-6 * (l + 1)), l
+
+
+@pytest.mark.parametrize("lmax", [0, 9, 17, 24])
+def test_core_complex_and_spinor_by_recurrence(core, orc, lmax):
+    """Complex and spinor harmonics built on the recurrence core, against the
+    oracle's complex definition and its eq. spinorial composition; every spinor
+    entry written exactly once."""
+    core.core_complex_rec.argtypes = [ctypes.c_long, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]
+    core.core_spinor_rec.argtypes = [ctypes.c_long, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                     ctypes.c_void_p]
+    u = _units(_pts()[:3000], np.float64)
+    n, F, S = u.shape[0], (lmax + 1) ** 2, 2 * (lmax + 1) ** 2
+    out = np.full((F, n, 2), np.nan)
+    core.core_complex_rec(n, u.ctypes.data, lmax, out.ctypes.data)
+    re, im = orc.eval_complex_xyz(lmax, u)
+    assert np.abs(out[..., 0].astype(LD) - re).max() <= 1e-13
+    assert np.abs(out[..., 1].astype(LD) - im).max() <= 1e-13
+    sp = np.full((S, 2, n, 2), np.nan)
+    count = np.zeros((S, 2, n), dtype=np.int32)
+    core.core_spinor_rec(n, u.ctypes.data, lmax, sp.ctypes.data, count.ctypes.data)
+    assert (count == 1).all()
+    sre, sim = orc.eval_spinor_xyz(lmax, u)
+    assert np.abs(sp[..., 0].astype(LD) - sre).max() <= 1e-13
+    assert np.abs(sp[..., 1].astype(LD) - sim).max() <= 1e-13

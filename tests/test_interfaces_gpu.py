@@ -151,3 +151,37 @@ def test_recurrence_fp32(dev, orc, lmax, n_random):
     if lmax <= 9:  # the explicit FP32 formulas agree within both bounds
         ex = sh.sh_eval_f32(lmax, torch.from_numpy(pts).to(dev)).cpu().numpy()
         assert np.abs(got - ex).max() <= 1e-5
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("lmax", [3, 12, 24])
+def test_complex_and_spinor_by_recurrence(dev, orc, dtype, lmax):
+    """Complex and spinor harmonics up to l = 24 by recurrence, through the three
+    input interfaces, against the oracle; tolerance 1e-13 in FP64 and the FP32
+    recurrence bound (5e-6 up to l = 9, 1e-6 (l + 1) beyond) in FP32."""
+    tol = 1e-13 if dtype == np.float64 else max(5e-6, 1e-6 * (lmax + 1))
+    pts = workloads.points_plain_eval(seed=6, n_random=4001).astype(dtype)  # odd count
+    x = torch.from_numpy(pts).to(dev)
+    re, im = orc.eval_complex_xyz(lmax, pts.astype(np.float64))
+    got = sh.sh_eval_complex_rec(lmax, x).cpu().numpy()
+    assert np.abs(got.real.astype(LD) - re).max() <= tol
+    assert np.abs(got.imag.astype(LD) - im).max() <= tol
+    sre, sim = orc.eval_spinor_xyz(lmax, pts.astype(np.float64))
+    gs = sh.sh_eval_spinor_rec(lmax, x).cpu().numpy()
+    assert np.abs(gs.real.astype(LD) - sre).max() <= tol
+    assert np.abs(gs.imag.astype(LD) - sim).max() <= tol
+    u = _units(2000, 90, dtype)
+    re, im = orc.eval_complex_xyz(lmax, u.astype(np.float64))
+    got = sh.sh_eval_complex_rec(lmax, torch.from_numpy(u).to(dev), input_kind=sh.SH_IN_UNIT).cpu().numpy()
+    assert np.abs(got.real.astype(LD) - re).max() <= tol
+    rng = np.random.default_rng(lmax)
+    th = np.arccos(rng.uniform(-1, 1, 2000)).astype(dtype)
+    ph = rng.uniform(-np.pi, np.pi, 2000).astype(dtype)
+    sre, sim = orc.eval_spinor_angles(lmax, th.astype(LD), ph.astype(LD))
+    gs = sh.sh_eval_spinor_rec(lmax, torch.from_numpy(th).to(dev), torch.from_numpy(ph).to(dev),
+                               input_kind=sh.SH_IN_ANGLES).cpu().numpy()
+    assert np.abs(gs.real.astype(LD) - sre).max() <= tol
+    assert np.abs(gs.imag.astype(LD) - sim).max() <= tol
+    if lmax <= 9:  # agrees with the explicit forms
+        ex = sh.sh_eval_complex(lmax, x) if dtype == np.float64 else sh.sh_eval_complex_f32(lmax, x)
+        assert np.abs(sh.sh_eval_complex_rec(lmax, x).cpu().numpy() - ex.cpu().numpy()).max() <= 2 * tol
