@@ -158,6 +158,14 @@ int sh_eval_grad(int lmax, int64_t n, const double *xyz, const double *grad_out,
 int sh_eval_grad_f32(int lmax, int64_t n, const float *xyz, const float *grad_out, float *grad_xyz,
                      hipStream_t stream);
 
+/* Backward pass of sh_eval_rec / sh_eval_rec_f32 for 0 <= lmax <= SH_LMAX_REC:
+ * arguments, convention and origin as sh_eval_grad (sh_eval_grad_f32), with
+ * grad_out [(lmax+1)^2][n]. */
+int sh_eval_grad_rec(int lmax, int64_t n, const double *xyz, const double *grad_out, double *grad_xyz,
+                     hipStream_t stream);
+int sh_eval_grad_rec_f32(int lmax, int64_t n, const float *xyz, const float *grad_out, float *grad_xyz,
+                         hipStream_t stream);
+
 /* Values and their Cartesian Jacobian in one pass, for forces:
  *   out [F][n]      R_row(x_i)
  *   jac [3][F][n]   d R_row(x_i) / d x_{i,k} at jac[(k * F + row) * n + i]

@@ -25,7 +25,8 @@ __all__ = ["SH_F32", "SH_F64", "SH_LMAX", "SH_LMAX_REC", "Radial", "ShError", "S
            "sh_eval_spinor", "sh_eval_spinor_f32", "spinor_index", "sh_eval_complex_unit",
            "sh_eval_complex_angles", "sh_eval_spinor_unit", "sh_eval_spinor_angles",
            "SH_IN_XYZ", "SH_IN_UNIT", "SH_IN_ANGLES", "sh_eval_complex_rec", "sh_eval_spinor_rec",
-           "sh_eval_f32", "sh_eval_grad", "sh_eval_grad_f32", "sh_eval_jac", "sh_eval_ld",
+           "sh_eval_f32", "sh_eval_grad", "sh_eval_grad_f32", "sh_eval_grad_rec", "sh_eval_grad_rec_f32",
+           "sh_eval_jac", "sh_eval_ld",
            "sh_eval_rec", "sh_eval_rec_f32", "sh_eval_unit", "sh_eval_unit_f32",
            "sh_projectors", "sh_projectors_f32", "sh_radial_create", "sh_radial_destroy",
            "sh_strerror", "spherical_harmonics"]
@@ -316,29 +317,45 @@ def sh_eval_jac(lmax: int, xyz: torch.Tensor, out: torch.Tensor | None = None,
     return out, jac
 
 
+def sh_eval_grad_rec(lmax: int, xyz: torch.Tensor, grad_out: torch.Tensor, grad_xyz=None, stream=None):
+    """Backward pass of sh_eval_rec (lmax <= 24, float64)."""
+    return _grad("sh_eval_grad_rec", torch.float64, lmax, xyz, grad_out, grad_xyz, stream)
+
+
+def sh_eval_grad_rec_f32(lmax: int, xyz: torch.Tensor, grad_out: torch.Tensor, grad_xyz=None, stream=None):
+    """Backward pass of sh_eval_rec_f32 (lmax <= 24, float32)."""
+    return _grad("sh_eval_grad_rec_f32", torch.float32, lmax, xyz, grad_out, grad_xyz, stream)
+
+
 class SphericalHarmonics(torch.autograd.Function):
     """R_l^m(xyz) for l <= lmax as a differentiable op: forward is sh_eval
     (sh_eval_f32 for float32 points), the gradient with respect to the points is
-    sh_eval_grad (sh_eval_grad_f32)."""
+    sh_eval_grad (sh_eval_grad_f32); for 9 < lmax <= 24 the recurrence entries
+    sh_eval_rec(_f32) and sh_eval_grad_rec(_f32)."""
 
     @staticmethod
     def forward(ctx, xyz: torch.Tensor, lmax: int) -> torch.Tensor:
         xyz = xyz.contiguous()
         ctx.lmax = lmax
         ctx.save_for_backward(xyz)
-        return sh_eval(lmax, xyz) if xyz.dtype == torch.float64 else sh_eval_f32(lmax, xyz)
+        f64 = xyz.dtype == torch.float64
+        if lmax > SH_LMAX:
+            return sh_eval_rec(lmax, xyz) if f64 else sh_eval_rec_f32(lmax, xyz)
+        return sh_eval(lmax, xyz) if f64 else sh_eval_f32(lmax, xyz)
 
     @staticmethod
     def backward(ctx, grad_out: torch.Tensor):
         (xyz,) = ctx.saved_tensors
         g = grad_out.contiguous()
-        if xyz.dtype == torch.float64:
-            return sh_eval_grad(ctx.lmax, xyz, g), None
-        return sh_eval_grad_f32(ctx.lmax, xyz, g), None
+        f64 = xyz.dtype == torch.float64
+        if ctx.lmax > SH_LMAX:
+            return (sh_eval_grad_rec if f64 else sh_eval_grad_rec_f32)(ctx.lmax, xyz, g), None
+        return (sh_eval_grad if f64 else sh_eval_grad_f32)(ctx.lmax, xyz, g), None
 
 
 def spherical_harmonics(xyz: torch.Tensor, lmax: int) -> torch.Tensor:
-    """Differentiable real harmonics [F, n] of float64 or float32 points [n, 3]."""
+    """Differentiable real harmonics [F, n] of float64 or float32 points [n, 3],
+    lmax <= 24 (explicit formulas up to 9, the recurrence beyond)."""
     return SphericalHarmonics.apply(xyz, lmax)
 
 

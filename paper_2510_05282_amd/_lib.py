@@ -68,6 +68,9 @@ def lib() -> ctypes.CDLL:
     L.sh_eval_grad_f32.argtypes = [i32, i64, vp, vp, vp, vp]
     L.sh_eval_grad_f32.restype = i32
     L.sh_eval_jac.argtypes = [i32, i64, vp, vp, vp, vp]
+    for fn in ("sh_eval_grad_rec", "sh_eval_grad_rec_f32"):
+        getattr(L, fn).argtypes = [i32, i64, vp, vp, vp, vp]
+        getattr(L, fn).restype = i32
     L.sh_eval_jac.restype = i32
     L.sh_radial_create.argtypes = [i32, i32, i32, ctypes.c_double, vp, ctypes.POINTER(vp)]
     L.sh_radial_create.restype = i32

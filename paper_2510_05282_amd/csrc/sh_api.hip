@@ -95,6 +95,15 @@ static int projectors(int lmax, int n_atoms, const TIO *centers, const int64_t *
     return hip_status(shk::launch_projectors<TIO>(lmax, A, stream));
 }
 
+template <typename TIO>
+static int grad_rec(int lmax, int64_t n, const TIO *xyz, const TIO *grad_out, TIO *grad_xyz, hipStream_t stream)
+{
+    if (lmax < 0 || lmax > SH_LMAX_REC || n < 0) return SH_EINVAL;
+    if (n == 0) return SH_OK;
+    if (!xyz || !grad_out || !grad_xyz) return SH_EINVAL;
+    return hip_status(shk::launch_grad_rec<TIO>(lmax, n, xyz, grad_out, n, grad_xyz, stream));
+}
+
 }  // namespace
 
 extern "C" {
@@ -232,6 +241,18 @@ int sh_eval_grad_f32(int lmax, int64_t n, const float *xyz, const float *grad_ou
     if (n == 0) return SH_OK;
     if (!xyz || !grad_out || !grad_xyz) return SH_EINVAL;
     return hip_status(shk::launch_grad<float>(lmax, n, xyz, grad_out, n, grad_xyz, stream));
+}
+
+int sh_eval_grad_rec(int lmax, int64_t n, const double *xyz, const double *grad_out, double *grad_xyz,
+                     hipStream_t stream)
+{
+    return grad_rec<double>(lmax, n, xyz, grad_out, grad_xyz, stream);
+}
+
+int sh_eval_grad_rec_f32(int lmax, int64_t n, const float *xyz, const float *grad_out, float *grad_xyz,
+                         hipStream_t stream)
+{
+    return grad_rec<float>(lmax, n, xyz, grad_out, grad_xyz, stream);
 }
 
 int sh_eval_jac(int lmax, int64_t n, const double *xyz, double *out, double *jac, hipStream_t stream)

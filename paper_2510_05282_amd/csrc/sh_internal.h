@@ -44,6 +44,11 @@ hipError_t launch_fwd_spinor(int lmax, int64_t n, int input, const TIO* in0, con
 // Real harmonics up to lmax <= SH_LMAX_REC by recurrence.
 template <typename TIO>
 hipError_t launch_rec(int lmax, int64_t n, const TIO* xyz, TIO* out, int64_t ld, hipStream_t s);
+// Backward pass of launch_rec (lmax <= SH_LMAX_REC), arguments as launch_grad.
+template <typename TIO>
+hipError_t launch_grad_rec(int lmax, int64_t n, const TIO* xyz, const TIO* G, int64_t ldg, TIO* gxyz,
+                           hipStream_t s);
+
 // Complex and spinor harmonics by recurrence (lmax <= SH_LMAX_REC), inputs and
 // layout as launch_fwd_complex / launch_fwd_spinor.
 template <typename TIO>

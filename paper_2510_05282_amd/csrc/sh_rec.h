@@ -13,7 +13,8 @@ namespace shk {
 // All (lmax+1)^2 values at the unit vector (x, y, z); store(l, m, value), and for
 // m > 0 the value of +m comes just before that of -m.  keep
 // masks the m = 0 rows of l > 0 at the origin, as in eval_unit.  T is double or a
-// clang vector of doubles (that many points at once).  The loops run over the
+// clang vector of doubles (that many points at once), or a dual number of them
+// (every constant multiplies from the left).  The loops run over the
 // runtime lmax; every coefficient is a table entry indexed by (l, m) alone, so
 // within a wave it is one scalar load.
 template <typename T, typename Store>
@@ -34,7 +35,7 @@ __host__ __device__ __forceinline__ void eval_unit_rec(T x, T y, T z, T keep, in
             if (l == m) {
                 yl = T(d);
             } else if (l == m + 1) {
-                yl = S(shc::kRecE[m]) * z * d;
+                yl = (S(shc::kRecE[m]) * d) * z;
                 y2 = y1;
                 y1 = yl;
             } else {

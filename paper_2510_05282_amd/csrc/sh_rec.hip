@@ -25,6 +25,7 @@
 
 #include "../../include/shmi.h"
 #include "sh_core.h"
+#include "sh_dual.h"
 #include "sh_fwd.h"
 #include "sh_internal.h"
 #include "sh_rec.h"
@@ -82,6 +83,57 @@ hipError_t launch_rec(int lmax, int64_t n, const TIO* xyz, TIO* out, int64_t ld,
 
 template hipError_t launch_rec<double>(int, int64_t, const double*, double*, int64_t, hipStream_t);
 template hipError_t launch_rec<float>(int, int64_t, const float*, float*, int64_t, hipStream_t);
+
+// Backward pass by recurrence: the vector-Jacobian product of sh_eval_rec,
+//     g = (1/r) (v - u (u . v)),   v = sum_rows G[row] grad_u P_row(u),
+// as the explicit backward kernel, with grad_u P from the recurrence run on dual
+// numbers (value and the three partials in u).  One point per lane; the
+// normalisation and 1/r in FP64.
+template <typename TIO>
+__global__ __launch_bounds__(kRecBlock) void grad_rec_kernel(const TIO* __restrict__ xyz, const TIO* __restrict__ G,
+                                                             TIO* __restrict__ gxyz, uint32_t n, int64_t ldg,
+                                                             int lmax)
+{
+    const uint32_t i = blockIdx.x * kRecBlock + threadIdx.x;
+    if (i >= n) return;
+    const TIO* p = xyz + 3 * size_t(i);
+    double xb, yb, zb, keep, rinv;
+    normalize(double(p[0]), double(p[1]), double(p[2]), xb, yb, zb, keep, rinv);
+    using D = Dual<TIO, 3>;
+    const D x = D::var(TIO(xb), 0), y = D::var(TIO(yb), 1), z = D::var(TIO(zb), 2), k = D(TIO(keep));
+    TIO vx = TIO(0), vy = TIO(0), vz = TIO(0);
+    const uint32_t boff = i * uint32_t(sizeof(TIO));
+    eval_unit_rec<D>(x, y, z, k, lmax, [&](int l, int m, const D& P) {
+        const TIO g = *reinterpret_cast<const TIO*>(reinterpret_cast<const char*>(G + int64_t(row(l, m)) * ldg) + boff);
+        vx += g * P.d[0];
+        vy += g * P.d[1];
+        vz += g * P.d[2];
+    });
+    // at the origin rinv = 0, so the gradient is 0
+    const double uv = xb * double(vx) + yb * double(vy) + zb * double(vz);
+    TIO* o = gxyz + 3 * size_t(i);
+    o[0] = TIO(rinv * (double(vx) - xb * uv));
+    o[1] = TIO(rinv * (double(vy) - yb * uv));
+    o[2] = TIO(rinv * (double(vz) - zb * uv));
+}
+
+template <typename TIO>
+hipError_t launch_grad_rec(int lmax, int64_t n, const TIO* xyz, const TIO* G, int64_t ldg, TIO* gxyz, hipStream_t s)
+{
+    for (int64_t c0 = 0; c0 < n; c0 += kRecChunk) {
+        const int64_t nc = n - c0 < kRecChunk ? n - c0 : kRecChunk;
+        const unsigned grid = unsigned((nc + kRecBlock - 1) / kRecBlock);
+        hipLaunchKernelGGL((grad_rec_kernel<TIO>), dim3(grid), dim3(kRecBlock), 0, s, xyz + 3 * c0, G + c0,
+                           gxyz + 3 * c0, uint32_t(nc), ldg, lmax);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template hipError_t launch_grad_rec<double>(int, int64_t, const double*, const double*, int64_t, double*,
+                                            hipStream_t);
+template hipError_t launch_grad_rec<float>(int, int64_t, const float*, const float*, int64_t, float*, hipStream_t);
 
 // Complex (SPINOR = false) or spinor harmonics by recurrence, any input interface:
 // the lanes and layout of fwd_complex_kernel / fwd_spinor_kernel, lmax at run time.

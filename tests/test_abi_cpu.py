@@ -84,6 +84,10 @@ def test_radial_and_projector_validation(L):
 
 def test_grad_f32_and_jac_validation(L):
     fake = ctypes.c_void_p(0x1000)
+    for fn in ("sh_eval_grad_rec", "sh_eval_grad_rec_f32"):
+        assert getattr(L, fn)(25, 5, fake, fake, fake, None) == 1
+        assert getattr(L, fn)(24, 5, fake, None, fake, None) == 1
+        assert getattr(L, fn)(24, 0, None, None, None, None) == 0
     assert L.sh_eval_grad_f32(10, 5, fake, fake, fake, None) == 1
     assert L.sh_eval_grad_f32(3, 5, None, fake, fake, None) == 1
     assert L.sh_eval_grad_f32(3, 0, None, None, None, None) == 0

@@ -210,3 +210,27 @@ def test_core_complex_and_spinor_by_recurrence(core, orc, lmax):
     sre, sim = orc.eval_spinor_xyz(lmax, u)
     assert np.abs(sp[..., 0].astype(LD) - sre).max() <= 1e-13
     assert np.abs(sp[..., 1].astype(LD) - sim).max() <= 1e-13
+
+
+@pytest.mark.parametrize("lmax", [9, 24])
+def test_core_gradient_by_recurrence(core, orc, lmax):
+    """Recurrence on dual numbers: the contracted gradient at unit vectors against
+    the oracle, |dg|_inf <= 1e-12 (1 + |g|_inf) (FP64) and 2e-5 / 5e-6 (lmax + 1) (FP32)."""
+    for fn in ("core_grad_rec", "core_grad_rec_f32"):
+        getattr(core, fn).argtypes = [ctypes.c_long, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                      ctypes.c_void_p]
+    u = _units(_pts()[:3000], np.float64)
+    F = (lmax + 1) ** 2
+    G = np.random.default_rng(lmax).standard_normal((F, u.shape[0]))
+    out = np.empty((u.shape[0], 3))
+    core.core_grad_rec(u.shape[0], u.ctypes.data, lmax, G.ctypes.data, out.ctypes.data)
+    ref = orc.grad_xyz(lmax, u, G)
+    scale = 1 + np.abs(ref.astype(np.float64)).max(axis=1)
+    assert (np.abs(out.astype(LD) - ref).max(axis=1) / scale).max() <= 1e-12
+    u32, G32 = u.astype(np.float32), G.astype(np.float32)
+    out32 = np.empty((u.shape[0], 3), dtype=np.float32)
+    core.core_grad_rec_f32(u.shape[0], u32.ctypes.data, lmax, G32.ctypes.data, out32.ctypes.data)
+    ref32 = orc.grad_xyz(lmax, u32.astype(np.float64), G32.astype(np.float64))
+    scale32 = 1 + np.abs(ref32.astype(np.float64)).max(axis=1)
+    tol = 2e-5 if lmax <= 9 else 5e-6 * (lmax + 1)
+    assert (np.abs(out32.astype(LD) - ref32).max(axis=1) / scale32).max() <= tol

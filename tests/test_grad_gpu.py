@@ -173,3 +173,36 @@ def test_autograd_fp32(dev):
     G = torch.from_numpy(np.random.default_rng(13).standard_normal((25, 3000)).astype(np.float32)).to(dev)
     (y * G).sum().backward()
     assert torch.equal(x.grad, sh.sh_eval_grad_f32(4, x.detach(), G))
+
+
+@pytest.mark.parametrize("lmax", [4, 12, 24])
+def test_grad_by_recurrence(dev, orc, lmax):
+    """Backward pass up to l = 24 (recurrence on dual numbers) against the oracle's
+    analytic gradient (FP64 1e-12 (1 + |g|), FP32 2e-5 / 5e-6 (lmax + 1)), against
+    central differences of the GPU forward, and through torch autograd."""
+    F = (lmax + 1) ** 2
+    pts = np.concatenate([workloads.points_gradient(n=6000, seed=50 + lmax), np.zeros((1, 3))])
+    G = np.random.default_rng(lmax).standard_normal((F, pts.shape[0]))
+    x, Gt = torch.from_numpy(pts).to(dev), torch.from_numpy(G).to(dev)
+    g = sh.sh_eval_grad_rec(lmax, x, Gt).cpu().numpy()
+    assert _rel_err(g, orc.grad_xyz(lmax, pts, G)) <= 1e-12
+    assert np.all(g[-1] == 0)  # origin
+    if lmax <= 9:
+        assert _rel_err(g, sh.sh_eval_grad(lmax, x, Gt).cpu().numpy().astype(LD)) <= 1e-12
+    h = 1e-6
+    fd = np.zeros_like(g)
+    for k in range(3):
+        e = torch.zeros(3, dtype=torch.float64, device=dev)
+        e[k] = h
+        yp = sh.sh_eval_rec(lmax, (x + e).contiguous())
+        ym = sh.sh_eval_rec(lmax, (x - e).contiguous())
+        fd[:, k] = ((yp - ym) / (2 * h) * Gt).sum(0).cpu().numpy()
+    scale = 1 + np.abs(g).max(axis=1)
+    assert (np.abs(fd[:-1] - g[:-1]).max(axis=1) / scale[:-1]).max() <= 1e-6
+    xr = x.clone().requires_grad_(True)
+    (sh.spherical_harmonics(xr, lmax) * Gt).sum().backward()
+    assert torch.equal(xr.grad, torch.from_numpy(g).to(dev) if lmax > 9 else sh.sh_eval_grad(lmax, x, Gt))
+    p32, G32 = pts.astype(np.float32), G.astype(np.float32)
+    g32 = sh.sh_eval_grad_rec_f32(lmax, torch.from_numpy(p32).to(dev), torch.from_numpy(G32).to(dev)).cpu().numpy()
+    ref32 = orc.grad_xyz(lmax, p32.astype(np.float64), G32.astype(np.float64))
+    assert _rel_err(g32, ref32) <= (2e-5 if lmax <= 9 else 5e-6 * (lmax + 1))

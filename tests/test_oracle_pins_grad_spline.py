@@ -164,3 +164,26 @@ def test_projector_brute_force(orc):
                         yv = mp.re(1 / mp.sqrt(2) * (mp.spherharm(l, -m, th, ph)
                                                      + (-1) ** m * mp.spherharm(l, m, th, ph)))
                     assert abs(float(block[l * l + l + m, j]) - R * float(yv)) <= 1e-13
+
+
+def test_gradient_high_l_sum_rule_euler_and_differences(orc):
+    """The oracle's Jacobian up to l = 24 (beyond the explicit formulas): the sum
+    rule r^2 sum_m |grad R_l^m|^2 = l(l+1)(2l+1)/(4 pi), Euler's relation, and
+    fourth-order central differences of its own forward values."""
+    lmax = 24
+    pts = np.concatenate([workloads.isotropic_points(200, 0.5, 3, seed=28), np.array([[0, 0, 2.0], [1e-7, 0, 1]])])
+    J = orc.jacobian_xyz(lmax, pts)
+    r2 = (pts.astype(LD) ** 2).sum(1)
+    for l in range(lmax + 1):
+        sl = slice(l * l, (l + 1) * (l + 1))
+        s = r2 * (J[:, sl] ** 2).sum(axis=(0, 1))
+        ref = LD(l * (l + 1) * (2 * l + 1)) / (4 * PI_LD)
+        assert np.abs(s - ref).max() <= 1e-15 * max(1.0, float(ref)), l
+    assert np.abs((J * pts.T.astype(LD)[:, None, :]).sum(0)).max() <= 1e-15
+    h = 2.0**-18
+    for k in range(3):
+        e = np.zeros(3)
+        e[k] = h
+        f = {s: orc.eval_xyz(lmax, pts + s * e) for s in (-2, -1, 1, 2)}
+        fd = (-f[2] + 8 * f[1] - 8 * f[-1] + f[-2]) / (12 * LD(h))
+        assert np.abs(fd - J[k]).max() <= 1e-9
