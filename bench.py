@@ -300,6 +300,19 @@ def bench_gradient(sh, workloads, dev, steps):
     res["jacobian_ms"] = j * 1e3
     res["jacobian_points_per_s"] = n / j
     res["jacobian_frac"] = n * bj / j / 1e9 / HBM_PEAK_GBS
+    del jac, y
+    # backward beyond l = 9 (recurrence on dual numbers): lmax 16 on 2^22 points
+    nr, lr = n // 4, 16
+    Fr = (lr + 1) ** 2
+    xr = x[:nr].contiguous()
+    Gr = workloads.upstream_gradient_device(Fr, nr, seed=2, device=dev)
+    gr = torch.empty((nr, 3), dtype=torch.float64, device=dev)
+    _, per = time_launches(lambda: sh.sh_eval_grad_rec(lr, xr, Gr, grad_xyz=gr), steps, 2)
+    br = sum(per) / len(per)
+    bbr = 24 + Fr * 8 + 24
+    res["backward_rec_l16"] = {"n_points": nr, "ms": br * 1e3, "points_per_s": nr / br,
+                               "gbs": nr * bbr / br / 1e9, "frac": nr * bbr / br / 1e9 / HBM_PEAK_GBS,
+                               "bytes_per_point": bbr}
     return res
 
 
