@@ -313,6 +313,13 @@ def bench_gradient(sh, workloads, dev, steps):
     res["backward_rec_l16"] = {"n_points": nr, "ms": br * 1e3, "points_per_s": nr / br,
                                "gbs": nr * bbr / br / 1e9, "frac": nr * bbr / br / 1e9 / HBM_PEAK_GBS,
                                "bytes_per_point": bbr}
+    xr32, Gr32, gr32 = xr.float(), Gr.float(), gr.float()
+    _, per = time_launches(lambda: sh.sh_eval_grad_rec_f32(lr, xr32, Gr32, grad_xyz=gr32), steps, 2)
+    br32 = sum(per) / len(per)
+    bb32 = bbr // 2
+    res["backward_rec_l16_f32"] = {"n_points": nr, "ms": br32 * 1e3, "points_per_s": nr / br32,
+                                   "gbs": nr * bb32 / br32 / 1e9, "frac": nr * bb32 / br32 / 1e9 / HBM_PEAK_GBS,
+                                   "bytes_per_point": bb32}
     return res
 
 

@@ -12,9 +12,8 @@ namespace shk {
 
 // All (lmax+1)^2 values at the unit vector (x, y, z); store(l, m, value), and for
 // m > 0 the value of +m comes just before that of -m.  keep
-// masks the m = 0 rows of l > 0 at the origin, as in eval_unit.  T is double or a
-// clang vector of doubles (that many points at once), or a dual number of them
-// (every constant multiplies from the left).  The loops run over the
+// masks the m = 0 rows of l > 0 at the origin, as in eval_unit.  T is double, float
+// or a clang vector of them (that many points at once).  The loops run over the
 // runtime lmax; every coefficient is a table entry indexed by (l, m) alone, so
 // within a wave it is one scalar load.
 template <typename T, typename Store>
@@ -35,7 +34,7 @@ __host__ __device__ __forceinline__ void eval_unit_rec(T x, T y, T z, T keep, in
             if (l == m) {
                 yl = T(d);
             } else if (l == m + 1) {
-                yl = (S(shc::kRecE[m]) * d) * z;
+                yl = S(shc::kRecE[m]) * z * d;
                 y2 = y1;
                 y1 = yl;
             } else {
@@ -49,6 +48,69 @@ __host__ __device__ __forceinline__ void eval_unit_rec(T x, T y, T z, T keep, in
                 store(l, m, yl * c);
                 store(l, -m, yl * s);
             }
+        }
+    }
+}
+
+// v = sum over rows of G[row] grad_u P_row at the unit vector u = (x, y, z), for
+// 0 <= lmax <= kRecLmax, where P is the off-sphere extension the recurrence
+// evaluates: P_l^0 = Pb_l^0(z), P_l^m = Pb_l^m(z) C_m(x, y), P_l^-m = Pb_l^m(z) S_m(x, y)
+// with C_m + i S_m = (x + i y)^m.  Its partials are
+//     d(Pb C_m) = (m Pb C_{m-1}, -m Pb S_{m-1}, Pb' C_m),
+//     d(Pb S_m) = (m Pb S_{m-1},  m Pb C_{m-1}, Pb' S_m),
+// so per m only four sums over l are needed: a = sum G Pb and b = sum G Pb' for the
+// cosine (+m) and sine (-m) rows.  Pb' follows from differentiating the recurrence:
+// Pb_l' = A_l (Pb_{l-1} + z Pb_{l-1}' - B_l Pb_{l-2}').  g(row) returns G[row]; T is
+// double, float or a clang vector of them.
+template <typename T, typename GAt>
+__host__ __device__ __forceinline__ void grad_unit_rec(T x, T y, T z, int lmax, GAt&& g, T& vx, T& vy, T& vz)
+{
+    using S = scalar_t<T>;
+    const T zero = T(S(0));
+    vx = zero;
+    vy = zero;
+    vz = zero;
+    T c = T(S(1)), s = zero;  // C_m, S_m
+    for (int m = 0; m <= lmax; ++m) {
+        const T cp = c, sp = s;  // C_{m-1}, S_{m-1}
+        if (m > 0) {
+            c = x * cp - y * sp;
+            s = x * sp + y * cp;
+        }
+        const S d = S(shc::kRecD[m]);
+        T y1 = T(d), dy1 = zero, y2 = zero, dy2 = zero;  // Pb_{l-1}, Pb'_{l-1}, Pb_{l-2}, Pb'_{l-2}
+        T ac = zero, bc = zero, as = zero, bs = zero;
+        for (int l = m; l <= lmax; ++l) {
+            T yl, dl;
+            if (l == m) {
+                yl = T(d);
+                dl = zero;
+            } else {
+                const S a = l == m + 1 ? S(shc::kRecE[m]) : S(shc::kRecA[l][m]);
+                const S b = l == m + 1 ? S(0) : S(shc::kRecB[l][m]);
+                yl = a * (z * y1 - b * y2);
+                dl = a * (y1 + z * dy1 - b * dy2);
+                y2 = y1;
+                dy2 = dy1;
+                y1 = yl;
+                dy1 = dl;
+            }
+            const T gc = g(row(l, m));
+            ac += gc * yl;
+            bc += gc * dl;
+            if (m > 0) {
+                const T gs = g(row(l, -m));
+                as += gs * yl;
+                bs += gs * dl;
+            }
+        }
+        if (m == 0) {
+            vz += bc;
+        } else {
+            const S fm = S(m);
+            vx += fm * (ac * cp + as * sp);
+            vy += fm * (as * cp - ac * sp);
+            vz += bc * c + bs * s;
         }
     }
 }

@@ -25,7 +25,6 @@
 
 #include "../../include/shmi.h"
 #include "sh_core.h"
-#include "sh_dual.h"
 #include "sh_fwd.h"
 #include "sh_internal.h"
 #include "sh_rec.h"
@@ -86,46 +85,76 @@ template hipError_t launch_rec<float>(int, int64_t, const float*, float*, int64_
 
 // Backward pass by recurrence: the vector-Jacobian product of sh_eval_rec,
 //     g = (1/r) (v - u (u . v)),   v = sum_rows G[row] grad_u P_row(u),
-// as the explicit backward kernel, with grad_u P from the recurrence run on dual
-// numbers (value and the three partials in u).  One point per lane; the
-// normalisation and 1/r in FP64.
-template <typename TIO>
+// as the explicit backward kernel, with v from grad_unit_rec (the recurrence
+// differentiated in z, the xy factors by their closed-form partials).  PPL
+// adjacent points per lane (G read as one PPL-wide vector per row, 16 bytes for
+// two FP64 or four FP32 points), workgroups in XCD-contiguous order, no cap on
+// resident workgroups (capping to 2 or 4 per CU loses 25-50% here: the kernel
+// needs many loads in flight); the normalisation and 1/r in FP64.
+template <typename TIO, int PPL>
 __global__ __launch_bounds__(kRecBlock) void grad_rec_kernel(const TIO* __restrict__ xyz, const TIO* __restrict__ G,
                                                              TIO* __restrict__ gxyz, uint32_t n, int64_t ldg,
                                                              int lmax)
 {
-    const uint32_t i = blockIdx.x * kRecBlock + threadIdx.x;
-    if (i >= n) return;
-    const TIO* p = xyz + 3 * size_t(i);
-    double xb, yb, zb, keep, rinv;
-    normalize(double(p[0]), double(p[1]), double(p[2]), xb, yb, zb, keep, rinv);
-    using D = Dual<TIO, 3>;
-    const D x = D::var(TIO(xb), 0), y = D::var(TIO(yb), 1), z = D::var(TIO(zb), 2), k = D(TIO(keep));
-    TIO vx = TIO(0), vy = TIO(0), vz = TIO(0);
-    const uint32_t boff = i * uint32_t(sizeof(TIO));
-    eval_unit_rec<D>(x, y, z, k, lmax, [&](int l, int m, const D& P) {
-        const TIO g = *reinterpret_cast<const TIO*>(reinterpret_cast<const char*>(G + int64_t(row(l, m)) * ldg) + boff);
-        vx += g * P.d[0];
-        vy += g * P.d[1];
-        vz += g * P.d[2];
-    });
-    // at the origin rinv = 0, so the gradient is 0
-    const double uv = xb * double(vx) + yb * double(vy) + zb * double(vz);
-    TIO* o = gxyz + 3 * size_t(i);
-    o[0] = TIO(rinv * (double(vx) - xb * uv));
-    o[1] = TIO(rinv * (double(vy) - yb * uv));
-    o[2] = TIO(rinv * (double(vz) - zb * uv));
+    using V = typename vec_of<TIO, PPL>::type;
+    const uint32_t i0 = (xcd_tile(blockIdx.x, gridDim.x) * kRecBlock + threadIdx.x) * PPL;
+    if (i0 >= n) return;
+    double xb[PPL], yb[PPL], zb[PPL], rinv[PPL];
+    V x, y, z;
+#pragma unroll
+    for (int q = 0; q < PPL; ++q) {
+        const TIO* p = xyz + 3 * size_t(i0 + q);
+        double keep;  // not needed: rinv = 0 at the origin, so the gradient is 0 there
+        normalize(double(p[0]), double(p[1]), double(p[2]), xb[q], yb[q], zb[q], keep, rinv[q]);
+        lane<V, PPL>(x, q) = TIO(xb[q]);
+        lane<V, PPL>(y, q) = TIO(yb[q]);
+        lane<V, PPL>(z, q) = TIO(zb[q]);
+    }
+    const uint32_t boff = i0 * uint32_t(sizeof(TIO));
+    V vx, vy, vz;
+    grad_unit_rec<V>(x, y, z, lmax,
+                     [&](int r) {
+                         return __builtin_nontemporal_load(reinterpret_cast<const V*>(
+                             reinterpret_cast<const char*>(G + int64_t(r) * ldg) + boff));
+                     },
+                     vx, vy, vz);
+    TIO* o = gxyz + 3 * size_t(i0);
+#pragma unroll
+    for (int q = 0; q < PPL; ++q) {
+        const double gx = double(lane<V, PPL>(vx, q)), gy = double(lane<V, PPL>(vy, q)),
+                     gz = double(lane<V, PPL>(vz, q));
+        const double uv = xb[q] * gx + yb[q] * gy + zb[q] * gz;
+        o[3 * q + 0] = TIO(rinv[q] * (gx - xb[q] * uv));
+        o[3 * q + 1] = TIO(rinv[q] * (gy - yb[q] * uv));
+        o[3 * q + 2] = TIO(rinv[q] * (gz - zb[q] * uv));
+    }
+}
+
+// n must be a multiple of PPL (the caller sends the remainder to PPL = 1).
+template <typename TIO, int PPL>
+static hipError_t launch_grad_rec_one(int lmax, int64_t n, const TIO* xyz, const TIO* G, int64_t ldg, TIO* gxyz,
+                                      hipStream_t s)
+{
+    const unsigned grid = unsigned((n / PPL + kRecBlock - 1) / kRecBlock);
+    hipLaunchKernelGGL((grad_rec_kernel<TIO, PPL>), dim3(grid), dim3(kRecBlock), 0, s, xyz, G, gxyz, uint32_t(n),
+                       ldg, lmax);
+    return hipGetLastError();
 }
 
 template <typename TIO>
 hipError_t launch_grad_rec(int lmax, int64_t n, const TIO* xyz, const TIO* G, int64_t ldg, TIO* gxyz, hipStream_t s)
 {
-    for (int64_t c0 = 0; c0 < n; c0 += kRecChunk) {
+    constexpr int kVec = 16 / sizeof(TIO);
+    const bool vec_ok = ldg % kVec == 0 && reinterpret_cast<uintptr_t>(G) % 16 == 0;
+    for (int64_t c0 = 0; c0 < n; c0 += kRecChunk) {  // kRecChunk is a multiple of kVec
         const int64_t nc = n - c0 < kRecChunk ? n - c0 : kRecChunk;
-        const unsigned grid = unsigned((nc + kRecBlock - 1) / kRecBlock);
-        hipLaunchKernelGGL((grad_rec_kernel<TIO>), dim3(grid), dim3(kRecBlock), 0, s, xyz + 3 * c0, G + c0,
-                           gxyz + 3 * c0, uint32_t(nc), ldg, lmax);
-        const hipError_t e = hipGetLastError();
+        const int64_t nmain = vec_ok ? nc - nc % kVec : 0;
+        hipError_t e = hipSuccess;
+        if (nmain) e = launch_grad_rec_one<TIO, kVec>(lmax, nmain, xyz + 3 * c0, G + c0, ldg, gxyz + 3 * c0, s);
+        if (e == hipSuccess && nc > nmain) {
+            const int64_t c1 = c0 + nmain;
+            e = launch_grad_rec_one<TIO, 1>(lmax, nc - nmain, xyz + 3 * c1, G + c1, ldg, gxyz + 3 * c1, s);
+        }
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

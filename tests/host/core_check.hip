@@ -175,14 +175,10 @@ extern "C" void core_spinor_rec(long n, const double *u, int lmax, double *out, 
 template <typename T>
 static void grad_rec(long n, const T *u, int lmax, const T *G, T *out)
 {
-    using D = shk::Dual<T, 3>;
     for (long i = 0; i < n; ++i) {
-        const D x = D::var(u[3 * i], 0), y = D::var(u[3 * i + 1], 1), z = D::var(u[3 * i + 2], 2), k = D(T(1));
-        T v[3] = {T(0), T(0), T(0)};
-        shk::eval_unit_rec<D>(x, y, z, k, lmax, [&](int l, int m, const D &P) {
-            const T g = G[long(shk::row(l, m)) * n + i];
-            for (int q = 0; q < 3; ++q) v[q] += g * P.d[q];
-        });
+        T v[3];
+        shk::grad_unit_rec<T>(u[3 * i], u[3 * i + 1], u[3 * i + 2], lmax,
+                              [&](int r) { return G[long(r) * n + i]; }, v[0], v[1], v[2]);
         const T uv = u[3 * i] * v[0] + u[3 * i + 1] * v[1] + u[3 * i + 2] * v[2];
         for (int q = 0; q < 3; ++q) out[3 * i + q] = v[q] - u[3 * i + q] * uv;
     }

@@ -175,13 +175,16 @@ def test_autograd_fp32(dev):
     assert torch.equal(x.grad, sh.sh_eval_grad_f32(4, x.detach(), G))
 
 
+@pytest.mark.parametrize("n", [6000, 6003])
 @pytest.mark.parametrize("lmax", [4, 12, 24])
-def test_grad_by_recurrence(dev, orc, lmax):
-    """Backward pass up to l = 24 (recurrence on dual numbers) against the oracle's
+def test_grad_by_recurrence(dev, orc, lmax, n):
+    """Backward pass up to l = 24 (differentiated recurrence) against the oracle's
     analytic gradient (FP64 1e-12 (1 + |g|), FP32 2e-5 / 5e-6 (lmax + 1)), against
-    central differences of the GPU forward, and through torch autograd."""
+    central differences of the GPU forward, and through torch autograd.  n + 1
+    points (the last at the origin): 6001 takes the one-point-per-lane launch,
+    6004 the 2-point (FP64) and 4-point (FP32) one."""
     F = (lmax + 1) ** 2
-    pts = np.concatenate([workloads.points_gradient(n=6000, seed=50 + lmax), np.zeros((1, 3))])
+    pts = np.concatenate([workloads.points_gradient(n=n, seed=50 + lmax), np.zeros((1, 3))])
     G = np.random.default_rng(lmax).standard_normal((F, pts.shape[0]))
     x, Gt = torch.from_numpy(pts).to(dev), torch.from_numpy(G).to(dev)
     g = sh.sh_eval_grad_rec(lmax, x, Gt).cpu().numpy()
