@@ -87,10 +87,11 @@ template hipError_t launch_rec<float>(int, int64_t, const float*, float*, int64_
 //     g = (1/r) (v - u (u . v)),   v = sum_rows G[row] grad_u P_row(u),
 // as the explicit backward kernel, with v from grad_unit_rec (the recurrence
 // differentiated in z, the xy factors by their closed-form partials).  PPL
-// adjacent points per lane (G read as one PPL-wide vector per row, 16 bytes for
-// two FP64 or four FP32 points), workgroups in XCD-contiguous order, no cap on
-// resident workgroups (capping to 2 or 4 per CU loses 25-50% here: the kernel
-// needs many loads in flight); the normalisation and 1/r in FP64.
+// adjacent points per lane (G read as one PPL-wide vector per row: 16 bytes in
+// FP64, 8 in FP32, where four points per lane need 140 VGPRs and ran slower),
+// workgroups in XCD-contiguous order, no cap on resident workgroups (capping to
+// 2 or 4 per CU loses 25-50% here: the kernel needs many loads in flight); the
+// normalisation and 1/r in FP64.
 template <typename TIO, int PPL>
 __global__ __launch_bounds__(kRecBlock) void grad_rec_kernel(const TIO* __restrict__ xyz, const TIO* __restrict__ G,
                                                              TIO* __restrict__ gxyz, uint32_t n, int64_t ldg,
@@ -144,8 +145,8 @@ static hipError_t launch_grad_rec_one(int lmax, int64_t n, const TIO* xyz, const
 template <typename TIO>
 hipError_t launch_grad_rec(int lmax, int64_t n, const TIO* xyz, const TIO* G, int64_t ldg, TIO* gxyz, hipStream_t s)
 {
-    constexpr int kVec = 16 / sizeof(TIO);
-    const bool vec_ok = ldg % kVec == 0 && reinterpret_cast<uintptr_t>(G) % 16 == 0;
+    constexpr int kVec = 2;
+    const bool vec_ok = ldg % kVec == 0 && reinterpret_cast<uintptr_t>(G) % (kVec * sizeof(TIO)) == 0;
     for (int64_t c0 = 0; c0 < n; c0 += kRecChunk) {  // kRecChunk is a multiple of kVec
         const int64_t nc = n - c0 < kRecChunk ? n - c0 : kRecChunk;
         const int64_t nmain = vec_ok ? nc - nc % kVec : 0;

@@ -182,7 +182,7 @@ def test_grad_by_recurrence(dev, orc, lmax, n):
     analytic gradient (FP64 1e-12 (1 + |g|), FP32 2e-5 / 5e-6 (lmax + 1)), against
     central differences of the GPU forward, and through torch autograd.  n + 1
     points (the last at the origin): 6001 takes the one-point-per-lane launch,
-    6004 the 2-point (FP64) and 4-point (FP32) one."""
+    6004 the two-point one."""
     F = (lmax + 1) ** 2
     pts = np.concatenate([workloads.points_gradient(n=n, seed=50 + lmax), np.zeros((1, 3))])
     G = np.random.default_rng(lmax).standard_normal((F, pts.shape[0]))
