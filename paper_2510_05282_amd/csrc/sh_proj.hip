@@ -38,12 +38,14 @@ __global__ void spline_setup_kernel(const double* __restrict__ y, double2* __res
                  six_over_h2);
 }
 
-// Flat projector kernel over the concatenated atom point sets, one point per
-// lane.  The wave's first point locates its atom by a wave-wide search over the
-// CSR offsets; lanes past that atom's end search on their own.  A point whose
-// offsets are inconsistent (outside [offsets[a], offsets[a+1]) or beyond
-// n_points) is skipped, so every store stays inside out[F * n_points].
-template <int LMAX, typename TIO>
+// Flat projector kernel over the concatenated atom point sets, PPL adjacent
+// points per lane.  The wave's first point locates its atom by a wave-wide search
+// over the CSR offsets; lanes past that atom's end search on their own.  A lane
+// whose PPL points lie in one atom evaluates them together (proj_points); a lane
+// that straddles an atom boundary or the end of the points takes them one by one.
+// A point whose offsets are inconsistent (outside [offsets[a], offsets[a+1]) or
+// beyond n_points) is skipped, so every store stays inside out[F * n_points].
+template <int LMAX, typename TIO, int PPL>
 __global__ __launch_bounds__(256) void proj_kernel(const TIO* __restrict__ centers,
                                                    const int64_t* __restrict__ offsets, int n_atoms,
                                                    const TIO* __restrict__ points, int64_t n_points,
@@ -52,42 +54,82 @@ __global__ __launch_bounds__(256) void proj_kernel(const TIO* __restrict__ cente
                                                    SplineGrid g, TIO* __restrict__ out, int64_t j0)
 {
     constexpr int F = nfun(LMAX);
-    // first point of this wave; the launch covers points j0 .. j0 + 256 gridDim.x - 1
-    const int64_t w0 = j0 + int64_t(xcd_tile(blockIdx.x, gridDim.x)) * 256 + (threadIdx.x & ~63u);
+    // first point of this wave; the launch covers points j0 .. j0 + 256 PPL gridDim.x - 1
+    const int64_t w0 = j0 + (int64_t(xcd_tile(blockIdx.x, gridDim.x)) * 256 + (threadIdx.x & ~63u)) * PPL;
     if (w0 >= n_points) return;
-    const int64_t j = w0 + (threadIdx.x & 63);
+    const int64_t j = w0 + (threadIdx.x & 63) * PPL;
     const bool live = j < n_points;
-    const TIO* p = points + 3 * (live ? j : w0);
-    const double px = double(p[0]), py = double(p[1]), pz = double(p[2]);  // in flight during the search
+    double px[PPL], py[PPL], pz[PPL];  // in flight during the search
+#pragma unroll
+    for (int q = 0; q < PPL; ++q) {
+        const TIO* p = points + 3 * (live && j + q < n_points ? j + q : w0);
+        px[q] = double(p[0]);
+        py[q] = double(p[1]);
+        pz[q] = double(p[2]);
+    }
     const int aw = wave_search(offsets, n_atoms, w0);
     const int64_t aw_end = aw >= 0 ? offsets[aw + 1] : -1;
     if (!live) return;
+    auto table_of = [&](int a) {
+        const int t = table_of_atom ? table_of_atom[a] : a;
+        return table + int64_t(t < 0 ? 0 : (t >= n_tables ? n_tables - 1 : t)) * g.n_r * tab_ch;
+    };
+    auto center_of = [&](int a, double (&c)[3]) {
+        c[0] = double(centers[3 * a]);
+        c[1] = double(centers[3 * a + 1]);
+        c[2] = double(centers[3 * a + 2]);
+    };
     const int a = j < aw_end ? aw : lane_search(offsets, n_atoms, j);
     const int64_t o0 = offsets[a], o1 = offsets[a + 1];
-    if (!(o0 >= 0 && o0 <= j && j < o1 && o1 <= n_points)) return;
-    int t = table_of_atom ? table_of_atom[a] : a;
-    t = t < 0 ? 0 : (t >= n_tables ? n_tables - 1 : t);
-    const double c[3] = {double(centers[3 * a]), double(centers[3 * a + 1]), double(centers[3 * a + 2])};
-    proj_point<LMAX, TIO>(px, py, pz, c, table + int64_t(t) * g.n_r * tab_ch, tab_ch, g,
-                          out + F * o0 + (j - o0), o1 - o0);
+    if constexpr (PPL == 1) {
+        if (!(o0 >= 0 && o0 <= j && j < o1 && o1 <= n_points)) return;
+        double c[3];
+        center_of(a, c);
+        proj_point<LMAX, TIO>(px[0], py[0], pz[0], c, table_of(a), tab_ch, g, out + F * o0 + (j - o0), o1 - o0);
+    } else if (o0 >= 0 && o0 <= j && j + PPL <= o1 && o1 <= n_points) {
+        double c[3];
+        center_of(a, c);
+        proj_points<LMAX, TIO, PPL>(px, py, pz, c, table_of(a), tab_ch, g, out + F * o0 + (j - o0), o1 - o0);
+    } else {
+#pragma unroll
+        for (int q = 0; q < PPL; ++q) {
+            const int64_t jq = j + q;
+            if (jq >= n_points) break;
+            const int b = jq < aw_end ? aw : lane_search(offsets, n_atoms, jq);
+            const int64_t b0 = offsets[b], b1 = offsets[b + 1];
+            if (!(b0 >= 0 && b0 <= jq && jq < b1 && b1 <= n_points)) continue;
+            double c[3];
+            center_of(b, c);
+            proj_point<LMAX, TIO>(px[q], py[q], pz[q], c, table_of(b), tab_ch, g, out + F * b0 + (jq - b0),
+                                  b1 - b0);
+        }
+    }
 }
 
-// Points per launch: keeps each grid well inside the 32-bit work-item count of a dispatch.
+// Points per launch: keeps each grid well inside the 32-bit work-item count of a
+// dispatch (a multiple of every lane width, so only the last launch has a tail).
 constexpr int64_t kProjChunk = int64_t(1) << 28;
 
-template <int LMAX, typename TIO>
-static hipError_t launch_proj_l(const ProjArgs<TIO>& A, hipStream_t s)
+template <int LMAX, typename TIO, int P>
+static hipError_t launch_proj_p(const ProjArgs<TIO>& A, hipStream_t s)
 {
     const SplineGrid g{A.n_r, A.h, 1.0 / A.h, A.r_max, A.h * A.h / 6.0};
     for (int64_t j0 = 0; j0 < A.n_points; j0 += kProjChunk) {
         const int64_t nc = A.n_points - j0 < kProjChunk ? A.n_points - j0 : kProjChunk;
-        hipLaunchKernelGGL((proj_kernel<LMAX, TIO>), dim3(unsigned((nc + 255) / 256)), dim3(256), 0, s, A.centers,
-                           A.offsets, A.n_atoms, A.points, A.n_points, A.table, A.tab_ch, A.n_tables,
+        hipLaunchKernelGGL((proj_kernel<LMAX, TIO, P>), dim3(unsigned((nc + 256 * P - 1) / (256 * P))), dim3(256), 0,
+                           s, A.centers, A.offsets, A.n_atoms, A.points, A.n_points, A.table, A.tab_ch, A.n_tables,
                            A.table_of_atom, g, A.out, j0);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+template <int LMAX, typename TIO>
+static hipError_t launch_proj_l(const ProjArgs<TIO>& A, hipStream_t s)
+{
+    return A.n_points >= kProjVecPoints ? launch_proj_p<LMAX, TIO, kProjPpl<TIO>>(A, s)
+                                        : launch_proj_p<LMAX, TIO, 1>(A, s);
 }
 
 template <typename TIO>

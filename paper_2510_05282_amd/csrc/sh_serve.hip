@@ -4,8 +4,9 @@
 // A batch is a list of requests of any lmax and either dtype.  The requests are
 // grouped by (dtype, lmax) and each group gets one launch of the kernel built for
 // it (registers and occupancy sized for that lmax, no per-point dispatch); each
-// request is cut into 256-point tiles and every lane evaluates one point with the
-// same per-point projector code as sh_projectors.  Request descriptors and their
+// request is cut into tiles of 256 lanes x PPL adjacent points, evaluated with the
+// same projector code as sh_projectors (PPL as there: the vector width for a group
+// of at least kProjVecPoints points, else 1).  Request descriptors and their
 // first-tile indices travel host -> device in one copy through a pinned staging
 // buffer per slot (the slot is reused only after its previous batch has completed,
 // so the staging buffer is never overwritten in flight).
@@ -37,50 +38,70 @@ struct ServeDesc {
     int dtype;
 };
 
-template <int LMAX, typename TIO>
-__device__ __forceinline__ void serve_point(const ServeDesc& d, int64_t j)
-{
-    const SplineGrid g{d.n_r, d.h, d.inv_h, d.r_max, d.h2_over_6};
-    const TIO* p = static_cast<const TIO*>(d.points) + 3 * j;
-    proj_point<LMAX, TIO>(double(p[0]), double(p[1]), double(p[2]), d.c, d.tab, d.ch, g,
-                          static_cast<TIO*>(d.out) + j, d.n);
-}
-
-constexpr int kServeBlock = 256;  // points per tile and block
+constexpr int kServeBlock = 256;  // lanes per tile and block
 
 // One launch per (lmax, dtype) group of a batch: block b handles tile
 // xcd_tile(b) of the group (the tiles of one group cost the same, so
 // XCD-contiguous ranges stay balanced and each XCD keeps few requests' tables in
 // its L2), finds its request by a wave-wide search over the group's first-tile
-// indices and evaluates one point per lane.
-template <int LMAX, typename TIO>
+// indices and evaluates P adjacent points per lane (the request's last lane
+// repeats its last point in the slots past the end and stores only its own).
+template <int LMAX, typename TIO, int P>
 __global__ __launch_bounds__(kServeBlock) void serve_kernel(const ServeDesc* __restrict__ descs,
                                                             const int64_t* __restrict__ tile0, int n_items)
 {
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
     // tile0 is increasing with tile0[0] = 0 <= tile, so the search finds an item
     const ServeDesc& d = descs[wave_search(tile0, n_items, tile)];
-    const int64_t j = (tile - d.tile0) * kServeBlock + threadIdx.x;
+    const int64_t j = (tile - d.tile0) * (kServeBlock * P) + threadIdx.x * P;
     if (j < 0 || j >= d.n) return;
-    serve_point<LMAX, TIO>(d, j);
+    const SplineGrid g{d.n_r, d.h, d.inv_h, d.r_max, d.h2_over_6};
+    if constexpr (P == 1) {
+        const TIO* p = static_cast<const TIO*>(d.points) + 3 * j;
+        proj_point<LMAX, TIO>(double(p[0]), double(p[1]), double(p[2]), d.c, d.tab, d.ch, g,
+                              static_cast<TIO*>(d.out) + j, d.n);
+    } else {
+        const int nvalid = d.n - j < P ? int(d.n - j) : P;
+        const TIO* p = static_cast<const TIO*>(d.points) + 3 * j;
+        double px[P], py[P], pz[P];
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            const int qq = q < nvalid ? q : nvalid - 1;
+            px[q] = double(p[3 * qq]);
+            py[q] = double(p[3 * qq + 1]);
+            pz[q] = double(p[3 * qq + 2]);
+        }
+        proj_points<LMAX, TIO, P>(px, py, pz, d.c, d.tab, d.ch, g, static_cast<TIO*>(d.out) + j, d.n, nvalid);
+    }
 }
 
-template <typename TIO>
-static hipError_t launch_group(int lmax, int64_t tiles, const ServeDesc* descs, const int64_t* tile0, int n,
-                               hipStream_t s)
+template <int LMAX, typename TIO>
+static void launch_group_l(int ppl, int64_t tiles, const ServeDesc* descs, const int64_t* tile0, int n,
+                           hipStream_t s)
 {
     const dim3 grid = dim3(unsigned(tiles)), block = dim3(kServeBlock);
+    if (ppl == 1)
+        hipLaunchKernelGGL((serve_kernel<LMAX, TIO, 1>), grid, block, 0, s, descs, tile0, n);
+    else
+        hipLaunchKernelGGL((serve_kernel<LMAX, TIO, kProjPpl<TIO>>), grid, block, 0, s, descs, tile0, n);
+}
+
+// ppl is 1 or kProjPpl<TIO>
+template <typename TIO>
+static hipError_t launch_group(int lmax, int ppl, int64_t tiles, const ServeDesc* descs, const int64_t* tile0, int n,
+                               hipStream_t s)
+{
     switch (lmax) {
-    case 0: hipLaunchKernelGGL((serve_kernel<0, TIO>), grid, block, 0, s, descs, tile0, n); break;
-    case 1: hipLaunchKernelGGL((serve_kernel<1, TIO>), grid, block, 0, s, descs, tile0, n); break;
-    case 2: hipLaunchKernelGGL((serve_kernel<2, TIO>), grid, block, 0, s, descs, tile0, n); break;
-    case 3: hipLaunchKernelGGL((serve_kernel<3, TIO>), grid, block, 0, s, descs, tile0, n); break;
-    case 4: hipLaunchKernelGGL((serve_kernel<4, TIO>), grid, block, 0, s, descs, tile0, n); break;
-    case 5: hipLaunchKernelGGL((serve_kernel<5, TIO>), grid, block, 0, s, descs, tile0, n); break;
-    case 6: hipLaunchKernelGGL((serve_kernel<6, TIO>), grid, block, 0, s, descs, tile0, n); break;
-    case 7: hipLaunchKernelGGL((serve_kernel<7, TIO>), grid, block, 0, s, descs, tile0, n); break;
-    case 8: hipLaunchKernelGGL((serve_kernel<8, TIO>), grid, block, 0, s, descs, tile0, n); break;
-    case 9: hipLaunchKernelGGL((serve_kernel<9, TIO>), grid, block, 0, s, descs, tile0, n); break;
+    case 0: launch_group_l<0, TIO>(ppl, tiles, descs, tile0, n, s); break;
+    case 1: launch_group_l<1, TIO>(ppl, tiles, descs, tile0, n, s); break;
+    case 2: launch_group_l<2, TIO>(ppl, tiles, descs, tile0, n, s); break;
+    case 3: launch_group_l<3, TIO>(ppl, tiles, descs, tile0, n, s); break;
+    case 4: launch_group_l<4, TIO>(ppl, tiles, descs, tile0, n, s); break;
+    case 5: launch_group_l<5, TIO>(ppl, tiles, descs, tile0, n, s); break;
+    case 6: launch_group_l<6, TIO>(ppl, tiles, descs, tile0, n, s); break;
+    case 7: launch_group_l<7, TIO>(ppl, tiles, descs, tile0, n, s); break;
+    case 8: launch_group_l<8, TIO>(ppl, tiles, descs, tile0, n, s); break;
+    case 9: launch_group_l<9, TIO>(ppl, tiles, descs, tile0, n, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -113,6 +134,10 @@ public:
                 return;
             }
         }
+        if (!slots_.empty() && warm_up(slots_[0]) != hipSuccess) {
+            (void)hipGetLastError();
+            *status = SH_EHIP;
+        }
     }
     ~HipExecutor() override
     {
@@ -129,6 +154,8 @@ public:
     int64_t max_items() const override { return kMaxItems; }
     // a dispatch counts its work-items in 32 bits: tiles * 256 < 2^32
     int64_t max_tiles() const override { return (int64_t(1) << 24) - 1; }
+    // the smallest tile (one point per lane); longer tiles only lower the count, so
+    // the max_tiles bound stays safe
     int64_t tile_points() const override { return shk::kServeBlock; }
     void* arena_base() override { return arena_; }
 
@@ -142,47 +169,58 @@ public:
         for (size_t k = 0; k < n; ++k) order_[k] = int(k);
         auto key = [&](int k) { return items[k].atom.dtype * 16 + items[k].lmax; };
         std::stable_sort(order_.begin(), order_.end(), [&](int a, int b) { return key(a) < key(b); });
+        // groups (first item, points), then the lane width of each from its size
+        groups_.clear();
+        for (size_t k = 0; k < n; ++k) {
+            if (groups_.empty() || key(order_[k]) != key(order_[groups_.back().first]))
+                groups_.push_back({int(k), 0, 1});
+            groups_.back().tiles += items[order_[k]].atom.n;  // points, until turned into tiles below
+        }
+        for (Group& g : groups_) {
+            const bool f64 = items[order_[g.first]].atom.dtype == SH_F64;
+            g.ppl = g.tiles >= shk::kProjVecPoints ? (f64 ? shk::kProjPpl<double> : shk::kProjPpl<float>) : 1;
+            g.tiles = 0;
+        }
         // descriptors, then their first-tile indices (relative to their group), in one copy
         int64_t* tile0 = reinterpret_cast<int64_t*>(s.host + n);
-        groups_.clear();
-        int64_t tiles = 0;
-        for (size_t k = 0; k < n; ++k) {
-            const Item& it = items[order_[k]];
-            if (groups_.empty() || key(order_[k]) != key(order_[groups_.back().first])) {
-                groups_.push_back({int(k), 0});
-                tiles = 0;
+        for (size_t gi = 0; gi < groups_.size(); ++gi) {
+            Group& g = groups_[gi];
+            const size_t end = gi + 1 < groups_.size() ? size_t(groups_[gi + 1].first) : n;
+            const int64_t tp = int64_t(shk::kServeBlock) * g.ppl;
+            for (size_t k = size_t(g.first); k < end; ++k) {
+                const Item& it = items[order_[k]];
+                shk::ServeDesc& d = s.host[k];
+                memset(&d, 0, sizeof(d));
+                d.points = it.atom.points;
+                d.out = it.out;
+                d.tab = static_cast<const double2*>(it.atom.tab);
+                for (int q = 0; q < 3; ++q) d.c[q] = it.atom.c[q];
+                d.h = it.atom.h;
+                d.inv_h = 1.0 / it.atom.h;
+                d.r_max = it.atom.r_max;
+                d.h2_over_6 = it.atom.h * it.atom.h / 6.0;
+                d.n = it.atom.n;
+                d.tile0 = g.tiles;
+                tile0[k] = g.tiles;
+                d.n_r = it.atom.n_r;
+                d.ch = it.atom.tab_lmax + 1;
+                d.lmax = it.lmax;
+                d.dtype = it.atom.dtype;
+                g.tiles += (it.atom.n + tp - 1) / tp;
             }
-            shk::ServeDesc& d = s.host[k];
-            memset(&d, 0, sizeof(d));
-            d.points = it.atom.points;
-            d.out = it.out;
-            d.tab = static_cast<const double2*>(it.atom.tab);
-            for (int q = 0; q < 3; ++q) d.c[q] = it.atom.c[q];
-            d.h = it.atom.h;
-            d.inv_h = 1.0 / it.atom.h;
-            d.r_max = it.atom.r_max;
-            d.h2_over_6 = it.atom.h * it.atom.h / 6.0;
-            d.n = it.atom.n;
-            d.tile0 = tiles;
-            tile0[k] = tiles;
-            d.n_r = it.atom.n_r;
-            d.ch = it.atom.tab_lmax + 1;
-            d.lmax = it.lmax;
-            d.dtype = it.atom.dtype;
-            tiles += (it.atom.n + shk::kServeBlock - 1) / shk::kServeBlock;
-            groups_.back().second = tiles;
-            if (tiles > max_tiles()) return SH_EINVAL;
+            if (g.tiles > max_tiles()) return SH_EINVAL;
         }
         hipError_t e = hipMemcpyAsync(s.dev, s.host, (sizeof(shk::ServeDesc) + sizeof(int64_t)) * n,
                                       hipMemcpyHostToDevice, s.stream);
         const int64_t* dev_tile0 = reinterpret_cast<const int64_t*>(s.dev + n);
-        for (size_t g = 0; g < groups_.size() && e == hipSuccess; ++g) {
-            const int b = groups_[g].first;
-            const int m = (g + 1 < groups_.size() ? groups_[g + 1].first : int(n)) - b;
+        for (size_t gi = 0; gi < groups_.size() && e == hipSuccess; ++gi) {
+            const Group& g = groups_[gi];
+            const int b = g.first;
+            const int m = (gi + 1 < groups_.size() ? groups_[gi + 1].first : int(n)) - b;
             const shk::ServeDesc& d = s.host[b];
             e = d.dtype == SH_F64
-                    ? shk::launch_group<double>(d.lmax, groups_[g].second, s.dev + b, dev_tile0 + b, m, s.stream)
-                    : shk::launch_group<float>(d.lmax, groups_[g].second, s.dev + b, dev_tile0 + b, m, s.stream);
+                    ? shk::launch_group<double>(d.lmax, g.ppl, g.tiles, s.dev + b, dev_tile0 + b, m, s.stream)
+                    : shk::launch_group<float>(d.lmax, g.ppl, g.tiles, s.dev + b, dev_tile0 + b, m, s.stream);
         }
         if (e == hipSuccess) e = hipEventRecord(s.done, s.stream);
         if (e != hipSuccess) {
@@ -215,7 +253,32 @@ private:
     std::vector<Slot> slots_;
     void* arena_ = nullptr;
     std::vector<int> order_;                      // launch() scratch: items sorted by group
-    std::vector<std::pair<int, int64_t>> groups_;  // launch() scratch: (first item, tiles)
+    // One launch of every kernel variant against a single empty request (n = 0, so
+    // each block returns at once), at creation: the first launch of a kernel costs
+    // far more than later ones, and a variant first used in the middle of serving
+    // would stall that batch and every request queued behind it.
+    hipError_t warm_up(Slot& s)
+    {
+        memset(s.host, 0, sizeof(shk::ServeDesc) + sizeof(int64_t));  // desc.n = 0, tile0[0] = 0
+        hipError_t e = hipMemcpyAsync(s.dev, s.host, sizeof(shk::ServeDesc) + sizeof(int64_t),
+                                      hipMemcpyHostToDevice, s.stream);
+        const int64_t* tile0 = reinterpret_cast<const int64_t*>(s.dev + 1);
+        for (int lmax = 0; lmax <= SH_LMAX && e == hipSuccess; ++lmax) {
+            for (const int ppl : {1, shk::kProjPpl<double>})
+                if (e == hipSuccess) e = shk::launch_group<double>(lmax, ppl, 1, s.dev, tile0, 1, s.stream);
+            for (const int ppl : {1, shk::kProjPpl<float>})
+                if (e == hipSuccess) e = shk::launch_group<float>(lmax, ppl, 1, s.dev, tile0, 1, s.stream);
+        }
+        const hipError_t w = hipStreamSynchronize(s.stream);
+        return e != hipSuccess ? e : w;
+    }
+
+    struct Group {
+        int first;      // first item (in order_)
+        int64_t tiles;  // tiles of the group's launch
+        int ppl;        // points per lane
+    };
+    std::vector<Group> groups_;  // launch() scratch
 };
 
 }  // namespace

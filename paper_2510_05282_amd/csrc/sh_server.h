@@ -56,7 +56,7 @@ public:
     virtual int n_slots() const = 0;
     virtual int64_t max_items() const = 0;  // requests per batch
     virtual int64_t max_tiles() const = 0;    // tiles per batch
-    virtual int64_t tile_points() const = 0;  // points per tile
+    virtual int64_t tile_points() const = 0;  // points per tile (the smallest, if they differ)
     virtual void* arena_base() = 0;
     // Queue a batch on a free slot; returns an SH_* status.
     virtual int launch(int slot, const std::vector<Item>& items) = 0;

@@ -156,3 +156,76 @@ def test_large_mixed_batch_matches_projectors(dev):
         srv.release(t)
     srv.close()
     radial.close()
+
+
+def test_tiny_and_odd_requests_match_projectors(dev):
+    """Requests of 1 to 7, 513 and 1025 points in both dtypes (the last lane of a
+    request holds fewer points than the lane width; rows of odd length do not start
+    on a vector boundary) against sh_projectors on each atom alone."""
+    rng = np.random.default_rng(12)
+    sizes = [1, 2, 3, 4, 5, 6, 7, 513, 1025]
+    cases = [(n, dt, lmax) for n in sizes for dt in ("f64", "f32") for lmax in (2, 9)]
+    tabs = np.stack([workloads.radial_table(rng, 9, 2000, 3.0) for _ in cases])
+    radial = sh.Radial(tabs, 3.0)
+    srv = Server(1 << 30, n_slots=2)
+    atoms, dev_pts, centers = [], [], []
+    for k, (n, dt, lmax) in enumerate(cases):
+        c = rng.uniform(0.0, 10.0, size=3)
+        p = c + rng.uniform(-1.7, 1.7, size=(n, 3))
+        t = torch.from_numpy(p).to(dev, torch.float64 if dt == "f64" else torch.float32).contiguous()
+        dev_pts.append(t)
+        centers.append(c)
+        atoms.append(srv.add_atom(t, c, radial, table=k))
+    _say("case: tiny and odd requests,", len(cases))
+    tickets = [srv.submit(a, lmax) for a, (_, _, lmax) in zip(atoms, cases)]
+    for t in tickets:
+        assert srv.wait(t, 60) == DONE
+    for k, (t, (n, dt, lmax)) in enumerate(zip(tickets, cases)):
+        got = srv.result(t, lmax, n, torch.float64 if dt == "f64" else torch.float32).double()
+        toa = torch.tensor([k], dtype=torch.int32, device=dev)
+        ref = sh.sh_projectors(lmax, torch.tensor(centers[k][None], dtype=torch.float64, device=dev),
+                               torch.tensor([0, n], dtype=torch.int64, device=dev),
+                               dev_pts[k].double().contiguous(), radial, table_of_atom=toa)
+        tol = 1e-13 if dt == "f64" else 5e-6
+        assert (got.reshape(-1) - ref).abs().max().item() <= tol, (n, dt, lmax)
+        srv.release(t)
+    srv.close()
+    radial.close()
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_tiny_requests_in_a_large_group(dev, dt):
+    """Requests of 1 to 7 points batched with one of 2^20 + 7 points of the same
+    (dtype, lmax): the group is large enough for the launch with several adjacent
+    points per lane, so the tiny requests are single partial lanes of it.  Against
+    sh_projectors on each atom alone."""
+    rng = np.random.default_rng(13)
+    lmax = 4
+    sizes = [3, 1, 2, 5, 7, (1 << 20) + 7, 6, 4]
+    tabs = np.stack([workloads.radial_table(rng, 9, 2000, 3.0) for _ in sizes])
+    radial = sh.Radial(tabs, 3.0)
+    srv = Server(4 << 30, n_slots=1)
+    atoms, dev_pts, centers = [], [], []
+    for k, n in enumerate(sizes):
+        c = rng.uniform(0.0, 10.0, size=3)
+        t = torch.from_numpy(c + rng.uniform(-1.7, 1.7, size=(n, 3))).to(
+            dev, torch.float64 if dt == "f64" else torch.float32).contiguous()
+        dev_pts.append(t)
+        centers.append(c)
+        atoms.append(srv.add_atom(t, c, radial, table=k))
+    _say("case: tiny requests in a large group,", dt)
+    tickets = [srv.submit(a, lmax) for a in atoms]
+    for t in tickets:
+        assert srv.wait(t, 60) == DONE
+    _say("  batches:", srv.stats()["batches"])
+    for k, (t, n) in enumerate(zip(tickets, sizes)):
+        got = srv.result(t, lmax, n, torch.float64 if dt == "f64" else torch.float32).double()
+        toa = torch.tensor([k], dtype=torch.int32, device=dev)
+        ref = sh.sh_projectors(lmax, torch.tensor(centers[k][None], dtype=torch.float64, device=dev),
+                               torch.tensor([0, n], dtype=torch.int64, device=dev),
+                               dev_pts[k].double().contiguous(), radial, table_of_atom=toa)
+        tol = 1e-13 if dt == "f64" else 5e-6
+        assert (got.reshape(-1) - ref).abs().max().item() <= tol, (n, dt)
+        srv.release(t)
+    srv.close()
+    radial.close()
