@@ -261,9 +261,42 @@ def bench_projectors(sh, workloads, dev, steps):
     avg = sum(per) / len(per)
     bpp = 16 * 8 + 24
     rad.close()
-    return {"workload": "64 atoms, r=3 spheres on a 0.2 grid, lmax 3, FP64", "n_points": n,
-            "ms_per_build": avg * 1e3, "points_per_s": n / avg, "gbs": n * bpp / avg / 1e9,
-            "frac": n * bpp / avg / 1e9 / HBM_PEAK_GBS, "bytes_per_point": bpp}
+    res = {"workload": "64 atoms, r=3 spheres on a 0.2 grid, lmax 3, FP64", "n_points": n,
+           "ms_per_build": avg * 1e3, "points_per_s": n / avg, "gbs": n * bpp / avg / 1e9,
+           "frac": n * bpp / avg / 1e9 / HBM_PEAK_GBS, "bytes_per_point": bpp}
+    del out, p
+    # a large build (several adjacent points per lane): 64 atoms x 150k points uniform
+    # in balls of radius 3, one 10-channel table per atom
+    import numpy as np
+    na, per = 64, 150_000
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(1)
+    cen = 20.0 * torch.rand((na, 3), generator=gen, dtype=torch.float64, device=dev)
+    d = torch.randn((na * per, 3), generator=gen, dtype=torch.float64, device=dev)
+    d = d / d.norm(dim=1, keepdim=True) * (3.0 * torch.rand((na * per, 1), generator=gen, dtype=torch.float64,
+                                                            device=dev) ** (1 / 3))
+    pts = (cen.repeat_interleave(per, 0) + d).contiguous()
+    del d
+    offl = torch.arange(0, na + 1, dtype=torch.int64, device=dev) * per
+    rng = np.random.default_rng(0)
+    radl = sh.Radial(np.stack([workloads.radial_table(rng, 9, 2000, 3.0) for _ in range(na)]), 3.0)
+    nl = na * per
+    large = {"workload": "64 atoms x 150k points, balls of radius 3", "n_points": nl}
+    for name, lmax, dt in (("lmax6_f64", 6, torch.float64), ("lmax9_f64", 9, torch.float64),
+                           ("lmax6_f32", 6, torch.float32)):
+        F, sz = (lmax + 1) ** 2, (8 if dt == torch.float64 else 4)
+        pl, cl = pts.to(dt), cen.to(dt)
+        o = torch.empty(F * nl, dtype=dt, device=dev)
+        fn = sh.sh_projectors if dt == torch.float64 else sh.sh_projectors_f32
+        _, per_l = time_launches(lambda: fn(lmax, cl, offl, pl, radl, out=o), steps, 2)
+        t = sum(per_l) / len(per_l)
+        b = nl * (F + 3) * sz
+        large[name] = {"ms": t * 1e3, "gbs": b / t / 1e9, "frac": b / t / 1e9 / HBM_PEAK_GBS,
+                       "bytes_per_point": (F + 3) * sz}
+        del o, pl, cl
+    radl.close()
+    res["large_build"] = large
+    return res
 
 
 def bench_gradient(sh, workloads, dev, steps):
