@@ -229,3 +229,55 @@ def test_tiny_requests_in_a_large_group(dev, dt):
         srv.release(t)
     srv.close()
     radial.close()
+
+
+def test_full_workload_sampled(dev, orc):
+    """The serving benchmark's workload at full size and in its launch
+    configuration: 10,000 requests (lmax U{0..9}, n log-uniform in [1e3, 1e6], 80%
+    FP64, 383 GB of output), 64 GB budget, 3 stream slots, all submitted at once.
+    Every request completes; 16 sampled requests are kept and checked against the
+    oracle on 64 sampled points each (FP64 1e-13, FP32 5e-6 on the rounded points)."""
+    n_req = 10000
+    reqs = workloads.request_stream(n_req=n_req, rate=1.0, seed=0)
+    tabs = np.zeros((n_req, 10, 2000))
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(7)
+    pts = []
+    for k, r in enumerate(reqs):
+        tabs[k, : r.lmax + 1] = workloads.radial_table(np.random.default_rng(r.seed), r.lmax, 2000, 3.0)
+        d = torch.randn((r.n, 3), generator=gen, dtype=torch.float64, device=dev)
+        d = d / d.norm(dim=1, keepdim=True)
+        rr = 3.0 * torch.rand((r.n, 1), generator=gen, dtype=torch.float64, device=dev) ** (1 / 3)
+        dt = torch.float64 if r.dtype == "f64" else torch.float32
+        pts.append((torch.from_numpy(r.center).to(dev) + d * rr).to(dt).contiguous())
+    _say("case: full serving workload,", n_req, "requests,", sum(r.n for r in reqs), "points")
+    radial = sh.Radial(tabs, 3.0)
+    srv = Server(64 << 30, max_pending=n_req + 1, n_slots=3)
+    atoms = [srv.add_atom(p, r.center, radial, table=k) for k, (p, r) in enumerate(zip(pts, reqs))]
+    rng = np.random.default_rng(5)
+    sample = set(int(k) for k in rng.choice(n_req, 16, replace=False))
+    tickets = {}
+    for k, (a, r) in enumerate(zip(atoms, reqs)):
+        t = srv.submit(a, r.lmax, 0 if k in sample else SH_REQ_AUTORELEASE)
+        if k in sample:
+            tickets[k] = t
+    srv.drain(600)
+    st = srv.stats()
+    _say("  batches:", st["batches"], "completed:", st["completed"], "failed:", st["failed"])
+    assert st["completed"] == n_req and st["failed"] == 0
+    for k, t in tickets.items():
+        r = reqs[k]
+        assert srv.poll(t) == DONE
+        dt = torch.float64 if r.dtype == "f64" else torch.float32
+        idx = np.sort(rng.choice(r.n, min(64, r.n), replace=False))
+        it = torch.from_numpy(idx).to(dev)
+        got = srv.result(t, r.lmax, r.n, dt)[:, it].double().cpu().numpy()
+        p = pts[k][it].double().cpu().numpy()
+        ref = orc.projectors(r.lmax, np.asarray(r.center)[None], np.array([0, idx.size]), p,
+                             tabs[k: k + 1, : r.lmax + 1], 3.0)
+        F = (r.lmax + 1) ** 2
+        err = float(np.abs(got.astype(LD) - ref.reshape(F, idx.size)).max())
+        assert err <= (1e-13 if r.dtype == "f64" else 5e-6), (k, r.lmax, r.dtype, err)
+        srv.release(t)
+    srv.close()
+    radial.close()
