@@ -13,9 +13,10 @@
 // lookups touch one or two cache lines.
 //
 // Launch (measured on MI355X, 64 atoms / 0.9M points / lmax 3: 43 us -> 30 us):
-// one point per lane; workgroups remapped so each XCD works through one
-// contiguous range of atoms (their tables then stay in that XCD's L2); the atom
-// of a wave found by one wave-wide search; plain stores.
+// workgroups remapped so each XCD works through one contiguous range of atoms
+// (their tables then stay in that XCD's L2); the atom of a wave found by one
+// wave-wide search; plain stores; one point per lane, or, for builds of at least
+// kProjVecPoints points, kProjPpl adjacent points per lane evaluated together.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
