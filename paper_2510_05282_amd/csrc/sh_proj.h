@@ -174,6 +174,21 @@ __device__ __forceinline__ int wave_search(const int64_t* __restrict__ keys, int
     return keys[lo] <= x ? lo : -1;
 }
 
+// The value v holds in lane k of the wave; k must be the same in every lane (one
+// scalar read per 32 bits, no memory access).
+template <typename T>
+__device__ __forceinline__ T lane_value(T v, int k)
+{
+    static_assert(sizeof(T) % 4 == 0, "32-bit words");
+    int w[sizeof(T) / 4];
+    __builtin_memcpy(w, &v, sizeof(T));
+#pragma unroll
+    for (int q = 0; q < int(sizeof(T) / 4); ++q) w[q] = __builtin_amdgcn_readlane(w[q], k);
+    T r;
+    __builtin_memcpy(&r, w, sizeof(T));
+    return r;
+}
+
 // The same for one lane (binary search): the last k in [0, n) with keys[k] <= x, or 0.
 __device__ __forceinline__ int lane_search(const int64_t* __restrict__ keys, int n, int64_t x)
 {

@@ -93,6 +93,27 @@ def test_small_and_odd_atoms(dev, orc, lmax, dtype):
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_more_than_64_atoms(dev, orc, dtype):
+    """100 atoms of 0 to 39 points (more atoms than lanes in a wave: the atom
+    search path rather than the per-lane preload), against the oracle."""
+    rng = np.random.default_rng(91)
+    sizes = rng.integers(0, 40, size=100)
+    sizes[[3, 50, 99]] = 0
+    centers = rng.uniform(0.0, 8.0, size=(100, 3))
+    pts = np.concatenate([c + rng.uniform(-1.7, 1.7, size=(k, 3)) for c, k in zip(centers, sizes)])
+    offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    tables = np.stack([workloads.radial_table(rng, 2, 300, 3.0) for _ in sizes])
+    if dtype == torch.float32:
+        pts = pts.astype(np.float32).astype(np.float64)
+        centers = centers.astype(np.float32).astype(np.float64)
+    A = workloads.AtomSet(2, centers, offsets, pts, tables, 3.0)
+    _say("case: 100 atoms,", int(offsets[-1]), "points,", dtype)
+    got = _run(dev, 2, A, dtype)
+    ref = orc.projectors(2, A.centers, A.offsets, A.points, A.tables, A.r_max)
+    assert np.abs(got.astype(LD) - ref).max() <= (1e-13 if dtype == torch.float64 else 5e-6)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_large_build_with_odd_atoms(dev, orc, dtype):
     """A build of over 2^20 points (the launch that evaluates several adjacent points
     per lane) whose atoms have odd sizes: lanes straddle atom boundaries and atom
