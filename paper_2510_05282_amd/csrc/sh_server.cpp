@@ -272,9 +272,17 @@ void Server::loop()
                 }
                 lk.lock();
             } else {
-                // nothing runs and nothing can be admitted: sleep until a submit,
-                // a release or shutdown changes the picture
+                // nothing runs and nothing can be admitted: watch for a submit, a
+                // release or shutdown with the lock free for up to kIdleSpin (a
+                // thread asleep on the condition variable takes microseconds to
+                // wake, which a lightly loaded server would add to every request),
+                // then sleep until one comes
                 const uint64_t g = gen_;
+                lk.unlock();
+                const auto t0 = std::chrono::steady_clock::now();
+                while (gen_ == g && !stop_ && std::chrono::steady_clock::now() - t0 < kIdleSpin)
+                    std::this_thread::yield();
+                lk.lock();
                 cv_work_.wait(lk, [&] { return stop_ || gen_ != g; });
             }
         }

@@ -138,6 +138,8 @@ private:
     int busy_slots_ = 0;
     int64_t refusals_ = 0;  // admission attempts refused for lack of budget
     std::atomic<uint64_t> gen_{0};  // bumped by every submit, release and shutdown
+    // how long an idle scheduler watches gen_ before it sleeps on cv_work_
+    static constexpr std::chrono::microseconds kIdleSpin{200};
     std::vector<int> busy_, done_;  // scratch of reap(): busy slots and their query results
     std::vector<double> lat_ms_;
     Stats st_{};
