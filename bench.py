@@ -185,8 +185,9 @@ def write_probe(buf, steps):
 def bench_interfaces(sh, xyz, out, steps):
     """lmax 9 through the other interfaces on the same points: unit vectors (no
     normalisation), angles (theta, phi), complex output (2^25 points, 16 B
-    per value), spinor output (2^23 points, 400 complex values each) and the
-    recurrence at lmax 16 (2^24 points)."""
+    per value), spinor output (2^23 points, 400 complex values each); the
+    recurrence at lmax 16 (2^24 points), and its complex (2^22 points) and spinor
+    (2^20 points, 1156 complex values each) harmonics."""
     import torch
     n = xyz.shape[0]
     r = xyz.norm(dim=1, keepdim=True)
@@ -244,6 +245,26 @@ def bench_interfaces(sh, xyz, out, steps):
     res["rec_l16_f32"] = {"n_points": nr, "points_per_s": nr / avg, "kernel_ms": avg * 1e3, "gbs": b / avg / 1e9,
                           "frac": b / avg / 1e9 / HBM_PEAK_GBS, "bytes_per_point": 12 + 289 * 4}
     del xr32
+    # complex and spinor harmonics by recurrence at lmax 16: 2^22 and 2^20 points
+    F16 = 289
+    nc16 = n // 16
+    occ = out.view(-1)[: 2 * F16 * nc16].view(torch.complex128).view(F16, nc16)
+    xcc = xyz[:nc16].contiguous()
+    _, per = time_launches(lambda: sh.sh_eval_complex_rec(16, xcc, out=occ), steps, 2)
+    avg = sum(per) / len(per)
+    b = nc16 * (24 + 16 * F16)
+    res["complex_rec_l16"] = {"n_points": nc16, "points_per_s": nc16 / avg, "kernel_ms": avg * 1e3,
+                              "gbs": b / avg / 1e9, "frac": b / avg / 1e9 / HBM_PEAK_GBS,
+                              "bytes_per_point": 24 + 16 * F16}
+    ns16 = n // 64
+    osp = out.view(-1)[: 8 * F16 * ns16].view(torch.complex128).view(2 * F16, 2, ns16)
+    xsp = xyz[:ns16].contiguous()
+    _, per = time_launches(lambda: sh.sh_eval_spinor_rec(16, xsp, out=osp), steps, 2)
+    avg = sum(per) / len(per)
+    b = ns16 * (24 + 64 * F16)
+    res["spinor_rec_l16"] = {"n_points": ns16, "points_per_s": ns16 / avg, "kernel_ms": avg * 1e3,
+                             "gbs": b / avg / 1e9, "frac": b / avg / 1e9 / HBM_PEAK_GBS,
+                             "bytes_per_point": 24 + 64 * F16}
     return res
 
 
