@@ -217,7 +217,9 @@ int sh_projectors(int lmax, int n_atoms, const double *centers, const int64_t *o
                   hipStream_t stream);
 
 /* Single-precision twin: float centers, points and out.  d = p - c, |d|, the
- * normalisation and the spline run in FP64; the harmonics and the product in FP32. */
+ * normalisation and the spline's interval run in FP64; the spline's cubic (from
+ * float copies of the tables the handle keeps), the harmonics and the product in
+ * FP32.  Same 5e-6 bound as sh_eval_f32 (times max(1, max|R_l|)). */
 int sh_projectors_f32(int lmax, int n_atoms, const float *centers, const int64_t *offsets, int64_t n_points,
                       const float *points, sh_radial_t radial, const int32_t *table_of_atom, float *out,
                       hipStream_t stream);

@@ -90,7 +90,10 @@ static int projectors(int lmax, int n_atoms, const TIO *centers, const int64_t *
     if (n_points == 0) return SH_OK;
     if (n_atoms == 0 || !centers || !offsets || !points || !out) return SH_EINVAL;
     if (!table_of_atom && radial->n_tables < n_atoms) return SH_EINVAL;
-    shk::ProjArgs<TIO> A{centers, offsets, n_atoms, points, n_points, radial->table, radial->lmax + 1,
+    const shk::knot_t<TIO>* table;
+    if constexpr (sizeof(TIO) == 8) table = radial->table;
+    else table = radial->table_f32;
+    shk::ProjArgs<TIO> A{centers, offsets, n_atoms, points, n_points, table, radial->lmax + 1,
                          radial->n_tables, table_of_atom, radial->n_r, radial->h, radial->r_max, out};
     return hip_status(shk::launch_projectors<TIO>(lmax, A, stream));
 }
@@ -273,11 +276,13 @@ int sh_radial_create(int lmax, int n_tables, int n_r, double r_max, const double
     const int64_t nval = n_ch * n_r;
     if (n_ch > 0x7fffffff || nval > (int64_t(1) << 34)) return SH_EINVAL;
     double2 *table = nullptr;
+    float2 *table_f32 = nullptr;
     double *y = nullptr, *scratch = nullptr;
     hipStream_t st = nullptr;
     int rc = SH_OK;
     hipError_t e;
     if (hipMalloc(&table, sizeof(double2) * nval) != hipSuccess ||
+        hipMalloc(&table_f32, sizeof(float2) * nval) != hipSuccess ||
         hipMalloc(&y, sizeof(double) * nval) != hipSuccess ||
         hipMalloc(&scratch, sizeof(double) * nval) != hipSuccess) {
         (void)hipGetLastError();
@@ -288,6 +293,7 @@ int sh_radial_create(int lmax, int n_tables, int n_r, double r_max, const double
     if (e == hipSuccess) e = hipMemcpyAsync(y, host_values, sizeof(double) * nval, hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
         e = shk::launch_spline_setup(y, table, scratch, int(n_ch), lmax + 1, n_r, r_max / double(n_r - 1), st);
+    if (e == hipSuccess) e = shk::launch_narrow_tables(table, table_f32, nval, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     rc = hip_status(e);
 done:
@@ -296,11 +302,14 @@ done:
     if (scratch) (void)hipFree(scratch);
     if (rc != SH_OK) {
         if (table) (void)hipFree(table);
+        if (table_f32) (void)hipFree(table_f32);
         return rc;
     }
-    sh_radial *h = new (std::nothrow) sh_radial{lmax, n_tables, n_r, r_max, r_max / double(n_r - 1), table};
+    sh_radial *h = new (std::nothrow) sh_radial{lmax, n_tables, n_r, r_max, r_max / double(n_r - 1), table,
+                                                table_f32};
     if (!h) {
         (void)hipFree(table);
+        (void)hipFree(table_f32);
         return SH_ENOMEM;
     }
     *out = h;
@@ -311,8 +320,9 @@ int sh_radial_destroy(sh_radial_t radial)
 {
     if (!radial) return SH_OK;
     hipError_t e = hipFree(radial->table);
+    const hipError_t e2 = hipFree(radial->table_f32);
     delete radial;
-    return hip_status(e);
+    return hip_status(e != hipSuccess ? e : e2);
 }
 
 int sh_projectors(int lmax, int n_atoms, const double *centers, const int64_t *offsets, int64_t n_points,
@@ -389,7 +399,9 @@ int sh_server_add_atom(sh_server_t srv, int dtype, int64_t n, const void *points
     for (int q = 0; q < 3; ++q) a.c[q] = center[q];
     if (radial) {
         if (table < 0 || table >= radial->n_tables) return SH_EINVAL;
-        a.tab = radial->table + int64_t(table) * radial->n_r * (radial->lmax + 1);
+        const int64_t t0 = int64_t(table) * radial->n_r * (radial->lmax + 1);
+        if (dtype == SH_F64) a.tab = radial->table + t0;
+        else a.tab = radial->table_f32 + t0;
         a.tab_lmax = radial->lmax;
         a.n_r = radial->n_r;
         a.h = radial->h;

@@ -11,10 +11,16 @@ struct sh_radial {
     int n_r;       // knots per channel (uniform grid on [0, r_max])
     double r_max;
     double h;      // knot spacing r_max / (n_r - 1)
-    double2* table;  // device, [n_tables][n_r][lmax+1] of (y, M)
+    double2* table;      // device, [n_tables][n_r][lmax+1] of (y, M)
+    float2* table_f32;   // the same pairs rounded to float, read by the FP32 kernels
 };
 
 namespace shk {
+
+// Knot pair type of the radial tables an FP64 or FP32 kernel reads.
+template <typename TIO> struct Knot { using type = double2; };
+template <> struct Knot<float> { using type = float2; };
+template <typename TIO> using knot_t = typename Knot<TIO>::type;
 
 // Forward values R_l^m for l <= lmax at n points xyz[n][3] into out[F][ld].
 template <typename TIO>
@@ -69,7 +75,7 @@ struct ProjArgs {
     int n_atoms;
     const TIO* points;             // [n_points][3]
     int64_t n_points;
-    const double2* table;          // radial handle's tables
+    const knot_t<TIO>* table;      // radial handle's tables (the float copy for FP32)
     int tab_ch;                    // channels per table
     int n_tables;
     const int32_t* table_of_atom;  // [n_atoms] or null (atom a uses table a)
@@ -80,6 +86,9 @@ struct ProjArgs {
 
 template <typename TIO>
 hipError_t launch_projectors(int lmax, const ProjArgs<TIO>& A, hipStream_t s);
+
+// table_f32[k] = table[k] rounded to float, k < n (device arrays).
+hipError_t launch_narrow_tables(const double2* table, float2* table_f32, int64_t n, hipStream_t s);
 
 // Natural-spline second derivatives for n_ch = n_tables * ch channels of n_r
 // values y[n_ch][n_r] (device): writes (y, M) pairs to table[n_tables][n_r][ch];

@@ -12,6 +12,7 @@
 
 #include "sh_core.h"
 #include "sh_fwd.h"
+#include "sh_internal.h"
 
 namespace shk {
 
@@ -44,6 +45,34 @@ __host__ __device__ __forceinline__ void spline_eval(const double2* __restrict__
         constexpr int L = decltype(lc)::value;
         const double2 a = k0[L], b = k1[L];
         R[L] = TIO(A * a.x + B * b.x + ((A * A * A - A) * a.y + (B * B * B - B) * b.y) * g.h2_over_6);
+    });
+}
+
+// The same from a table of float pairs, for the FP32 kernels: the interval i and
+// t = r/h - i in FP64 (near r_max, r/h is ~n_r, and float would leave t only a few
+// bits), the cubic in FP32.  Table values rounded to float and the FP32 cubic put
+// at most a few 1e-7 (of max|R|) into R, well inside the FP32 tolerance.
+template <int NL, typename TIO>
+__host__ __device__ __forceinline__ void spline_eval(const float2* __restrict__ tab, int ch, const SplineGrid& g,
+                                                     double r, TIO (&R)[NL])
+{
+    static_assert(sizeof(TIO) == 4, "float tables serve the FP32 kernels");
+    if (!(r <= g.r_max)) {
+        const float v = r != r ? float(r) : 0.0f;
+        static_for<0, NL>([&](auto lc) { R[decltype(lc)::value] = v; });
+        return;
+    }
+    const double q = r * g.inv_h;
+    int i = int(q);
+    i = i > g.n_r - 2 ? g.n_r - 2 : i;
+    const float t = float(q - double(i));
+    const float A = 1.0f - t, B = t, h26 = float(g.h2_over_6);
+    const float2* k0 = tab + int64_t(i) * ch;
+    const float2* k1 = k0 + ch;
+    static_for<0, NL>([&](auto lc) {
+        constexpr int L = decltype(lc)::value;
+        const float2 a = k0[L], b = k1[L];
+        R[L] = A * a.x + B * b.x + ((A * A * A - A) * a.y + (B * B * B - B) * b.y) * h26;
     });
 }
 
@@ -81,7 +110,7 @@ __host__ __device__ constexpr int l_of_row(int r)
 // row f goes to out[f * stride].
 template <int LMAX, typename TIO>
 __device__ __forceinline__ void proj_point(double px, double py, double pz, const double c[3],
-                                           const double2* __restrict__ tab, int ch, const SplineGrid& g,
+                                           const knot_t<TIO>* __restrict__ tab, int ch, const SplineGrid& g,
                                            TIO* __restrict__ out, int64_t stride)
 {
     const double dx = px - c[0], dy = py - c[1], dz = pz - c[2];
@@ -104,7 +133,7 @@ __device__ __forceinline__ void proj_point(double px, double py, double pz, cons
 // once per lane.
 template <int LMAX, typename TIO, int PPL>
 __device__ __forceinline__ void proj_points(const double (&px)[PPL], const double (&py)[PPL], const double (&pz)[PPL],
-                                            const double c[3], const double2* __restrict__ tab, int ch,
+                                            const double c[3], const knot_t<TIO>* __restrict__ tab, int ch,
                                             const SplineGrid& g, TIO* __restrict__ out, int64_t stride,
                                             int nvalid = PPL)
 {

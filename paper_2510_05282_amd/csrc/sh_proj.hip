@@ -67,7 +67,7 @@ template <int LMAX, typename TIO, int PPL, bool SMALL>
 __global__ __launch_bounds__(256) void proj_kernel(const TIO* __restrict__ centers,
                                                    const int64_t* __restrict__ offsets, int n_atoms,
                                                    const TIO* __restrict__ points, int64_t n_points,
-                                                   const double2* __restrict__ table, int tab_ch,
+                                                   const knot_t<TIO>* __restrict__ table, int tab_ch,
                                                    int n_tables, const int32_t* __restrict__ table_of_atom,
                                                    SplineGrid g, TIO* __restrict__ out, int64_t j0)
 {
@@ -206,6 +206,19 @@ hipError_t launch_projectors(int lmax, const ProjArgs<TIO>& A, hipStream_t s)
 
 template hipError_t launch_projectors<double>(int, const ProjArgs<double>&, hipStream_t);
 template hipError_t launch_projectors<float>(int, const ProjArgs<float>&, hipStream_t);
+
+__global__ void narrow_tables_kernel(const double2* __restrict__ in, float2* __restrict__ out, int64_t n)
+{
+    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k < n) out[k] = make_float2(float(in[k].x), float(in[k].y));
+}
+
+hipError_t launch_narrow_tables(const double2* table, float2* table_f32, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(narrow_tables_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, table, table_f32, n);
+    return hipGetLastError();
+}
 
 hipError_t launch_spline_setup(const double* y, double2* table, double* scratch, int n_ch, int ch, int n_r,
                                double h, hipStream_t s)

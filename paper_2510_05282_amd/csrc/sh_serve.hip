@@ -27,7 +27,7 @@ namespace shk {
 struct ServeDesc {
     const void* points;
     void* out;
-    const double2* tab;
+    const void* tab;  // knot_t of the request's dtype
     double c[3];
     double h, inv_h, r_max, h2_over_6;
     int64_t n;
@@ -58,8 +58,8 @@ __global__ __launch_bounds__(kServeBlock) void serve_kernel(const ServeDesc* __r
     const SplineGrid g{d.n_r, d.h, d.inv_h, d.r_max, d.h2_over_6};
     if constexpr (P == 1) {
         const TIO* p = static_cast<const TIO*>(d.points) + 3 * j;
-        proj_point<LMAX, TIO>(double(p[0]), double(p[1]), double(p[2]), d.c, d.tab, d.ch, g,
-                              static_cast<TIO*>(d.out) + j, d.n);
+        proj_point<LMAX, TIO>(double(p[0]), double(p[1]), double(p[2]), d.c,
+                              static_cast<const knot_t<TIO>*>(d.tab), d.ch, g, static_cast<TIO*>(d.out) + j, d.n);
     } else {
         const int nvalid = d.n - j < P ? int(d.n - j) : P;
         const TIO* p = static_cast<const TIO*>(d.points) + 3 * j;
@@ -71,7 +71,8 @@ __global__ __launch_bounds__(kServeBlock) void serve_kernel(const ServeDesc* __r
             py[q] = double(p[3 * qq + 1]);
             pz[q] = double(p[3 * qq + 2]);
         }
-        proj_points<LMAX, TIO, P>(px, py, pz, d.c, d.tab, d.ch, g, static_cast<TIO*>(d.out) + j, d.n, nvalid);
+        proj_points<LMAX, TIO, P>(px, py, pz, d.c, static_cast<const knot_t<TIO>*>(d.tab), d.ch, g,
+                                  static_cast<TIO*>(d.out) + j, d.n, nvalid);
     }
 }
 
@@ -193,7 +194,7 @@ public:
                 memset(&d, 0, sizeof(d));
                 d.points = it.atom.points;
                 d.out = it.out;
-                d.tab = static_cast<const double2*>(it.atom.tab);
+                d.tab = it.atom.tab;
                 for (int q = 0; q < 3; ++q) d.c[q] = it.atom.c[q];
                 d.h = it.atom.h;
                 d.inv_h = 1.0 / it.atom.h;

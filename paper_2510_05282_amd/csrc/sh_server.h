@@ -37,7 +37,8 @@ struct Atom {
     int64_t n;           // number of points
     const void* points;  // device [n][3]
     double c[3];         // centre
-    const void* tab;     // device (y, M) table of this atom's channels (double2), may be null (simulation)
+    const void* tab;     // device (y, M) table of this atom's channels (double2 for FP64 atoms, float2
+                         // for FP32 ones), may be null (simulation)
     int tab_lmax;        // channels - 1
     int n_r;
     double h, r_max;

@@ -120,8 +120,10 @@ extern "C" void core_spinor(long n, const double *u, int lmax, double *out, int 
 // Radial tables in the device layout: y[n_tables][4][n_r] -> interleaved
 // [n_tables][n_r][4] (y, M) by spline_solve, then R_0..R_3 of table t at r[k]:
 // out[k][4].
+// With f32 != 0 the pairs are rounded to float and evaluated by the FP32 lookup
+// the FP32 kernels use.
 extern "C" void core_spline4(int n_tables, int n_r, double r_max, const double *y, int t, long n, const double *r,
-                             double *out)
+                             double *out, int f32)
 {
     const int ch = 4;
     const double h = r_max / double(n_r - 1);
@@ -130,11 +132,19 @@ extern "C" void core_spline4(int n_tables, int n_r, double r_max, const double *
     for (int c = 0; c < n_tables * ch; ++c)
         shk::spline_solve(y + long(c) * n_r, tab.data() + long(c / ch) * n_r * ch + c % ch, ch, cc.data(), n_r,
                           6.0 / (h * h));
+    std::vector<float2> tabf(tab.size());
+    for (size_t k = 0; k < tab.size(); ++k) tabf[k] = make_float2(float(tab[k].x), float(tab[k].y));
     const shk::SplineGrid g{n_r, h, 1.0 / h, r_max, h * h / 6.0};
     for (long k = 0; k < n; ++k) {
-        double R[4];
-        shk::spline_eval<4, double>(tab.data() + long(t) * n_r * ch, ch, g, r[k], R);
-        for (int l = 0; l < 4; ++l) out[4 * k + l] = R[l];
+        if (f32) {
+            float R[4];
+            shk::spline_eval<4, float>(tabf.data() + long(t) * n_r * ch, ch, g, r[k], R);
+            for (int l = 0; l < 4; ++l) out[4 * k + l] = R[l];
+        } else {
+            double R[4];
+            shk::spline_eval<4, double>(tab.data() + long(t) * n_r * ch, ch, g, r[k], R);
+            for (int l = 0; l < 4; ++l) out[4 * k + l] = R[l];
+        }
     }
 }
 

@@ -156,9 +156,11 @@ def test_core_spinor(core, orc, lmax):
 
 def test_core_spline_interleaved_tables(core, orc):
     """The device spline (solve and lookup in the channel-interleaved table layout)
-    against the oracle's natural spline, every channel of several tables."""
+    against the oracle's natural spline, every channel of several tables: FP64
+    within 1e-13, and the FP32 lookup from float-rounded pairs within 5e-7 (the
+    tables are scaled to max|R_l| = 1)."""
     core.core_spline4.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_int,
-                                  ctypes.c_long, ctypes.c_void_p, ctypes.c_void_p]
+                                  ctypes.c_long, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
     rng = np.random.default_rng(12)
     n_tables, n_r, r_max = 3, 257, 3.0
     y = np.stack([workloads.radial_table(rng, 3, n_r, r_max) for _ in range(n_tables)])
@@ -167,11 +169,14 @@ def test_core_spline_interleaved_tables(core, orc):
     r = np.concatenate([rng.uniform(0, r_max, 4000), knots, [r_max, r_max * (1 + 1e-12), 4.0, 0.0]])
     for t in range(n_tables):
         out = np.empty((r.shape[0], 4))
-        core.core_spline4(n_tables, n_r, r_max, y.ctypes.data, t, r.shape[0], r.ctypes.data, out.ctypes.data)
+        core.core_spline4(n_tables, n_r, r_max, y.ctypes.data, t, r.shape[0], r.ctypes.data, out.ctypes.data, 0)
+        out32 = np.empty((r.shape[0], 4))
+        core.core_spline4(n_tables, n_r, r_max, y.ctypes.data, t, r.shape[0], r.ctypes.data, out32.ctypes.data, 1)
         for l in range(4):
             M = orc.spline_setup(y[t, l], r_max)
             ref = orc.spline_eval(y[t, l], M, r_max, r)
             assert np.abs(out[:, l].astype(LD) - ref).max() <= 1e-13, (t, l)
+            assert np.abs(out32[:, l].astype(LD) - ref).max() <= 5e-7, (t, l)
 
 
 @pytest.mark.parametrize("lmax", [9, 24])
