@@ -188,7 +188,9 @@ typedef struct sh_radial *sh_radial_t;
  * the knots r_i = i * r_max / (n_r - 1).  The library copies them to the device
  * and solves the natural-spline second derivatives there (on a private stream;
  * the call returns when the tables are ready).  The handle owns device memory
- * until sh_radial_destroy.  SH_EINVAL for lmax outside [0, 9], n_tables < 1,
+ * until sh_radial_destroy: the (y, M) pairs in double, 16 bytes per knot and
+ * channel, and a float copy of them for the FP32 kernels, 8 bytes more.  SH_EINVAL
+ * for lmax outside [0, 9], n_tables < 1,
  * n_r < 2, r_max not positive and finite, or NULL pointers; SH_ENOMEM when the
  * device allocation fails. */
 int sh_radial_create(int lmax, int n_tables, int n_r, double r_max, const double *host_values,
