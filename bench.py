@@ -379,26 +379,32 @@ def bench_gradient(sh, workloads, dev, steps):
 
 def bench_serving(sh, workloads, dev, n_req):
     """n_req projector requests (lmax ~ U{0..9}, n log-uniform in [1e3, 1e6], 80%
-    FP64), per-atom points and radial tables resident on the device, 64 GB budget.
+    FP64), per-atom points and radial tables (lmax + 1 channels) resident on the
+    device, 64 GB budget.
     First a closed loop (everything submitted at once) gives the saturation rate;
     then Poisson arrivals at 0.7x and 0.3x that rate give the latencies."""
     import numpy as np
     import torch
     from paper_2510_05282_amd.serve import SH_REQ_AUTORELEASE, Server
     reqs = workloads.request_stream(n_req=n_req, rate=1.0, seed=0)
-    tabs = np.zeros((n_req, 10, 2000))
+    # each request's own table of lmax + 1 channels: one radial handle per lmax
+    # holding the tables of that lmax's requests
+    slot = {}
+    by_l = {}
+    for k, r in enumerate(reqs):
+        slot[k] = (r.lmax, len(by_l.setdefault(r.lmax, [])))
+        by_l[r.lmax].append(workloads.radial_table(np.random.default_rng(r.seed), r.lmax, 2000, 3.0))
+    radials = {l: sh.Radial(np.stack(t), 3.0) for l, t in by_l.items()}
+    del by_l
     gen = torch.Generator(device=dev)
     gen.manual_seed(7)
     pts = []
     for k, r in enumerate(reqs):
-        rng = np.random.default_rng(r.seed)
-        tabs[k, : r.lmax + 1] = workloads.radial_table(rng, r.lmax, 2000, 3.0)
         dt = torch.float64 if r.dtype == "f64" else torch.float32
         d = torch.randn((r.n, 3), generator=gen, dtype=torch.float64, device=dev)
         d = d / d.norm(dim=1, keepdim=True)
         rr = 3.0 * torch.rand((r.n, 1), generator=gen, dtype=torch.float64, device=dev) ** (1 / 3)
         pts.append((torch.from_numpy(r.center).to(dev) + d * rr).to(dt).contiguous())
-    radial = sh.Radial(tabs, 3.0)
     total_points = sum(r.n for r in reqs)
     total_bytes = sum((r.lmax + 1) ** 2 * r.n * (8 if r.dtype == "f64" else 4) for r in reqs)
     out = {"workload": f"{n_req} projector requests, lmax U{{0..9}}, n log-U[1e3,1e6], 80% FP64, "
@@ -407,7 +413,8 @@ def bench_serving(sh, workloads, dev, n_req):
 
     def run(arrivals):
         srv = Server(64 << 30, max_pending=n_req + 1, n_slots=3)
-        atoms = [srv.add_atom(p, r.center, radial, table=k) for k, (p, r) in enumerate(zip(pts, reqs))]
+        atoms = [srv.add_atom(p, r.center, radials[slot[k][0]], table=slot[k][1])
+                 for k, (p, r) in enumerate(zip(pts, reqs))]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for a, r, ta in zip(atoms, reqs, arrivals):
@@ -436,7 +443,8 @@ def bench_serving(sh, workloads, dev, n_req):
                     "points_per_s": total_points / span, "gbs": total_bytes / span / 1e9,
                     "batches": st["batches"], "deferred": st["deferred"], "peak_bytes": st["peak_bytes"],
                     "completed": st["completed"], "failed": st["failed"]}
-    radial.close()
+    for rad in radials.values():
+        rad.close()
     return out
 
 

@@ -239,21 +239,23 @@ def test_full_workload_sampled(dev, orc):
     oracle on 64 sampled points each (FP64 1e-13, FP32 5e-6 on the rounded points)."""
     n_req = 10000
     reqs = workloads.request_stream(n_req=n_req, rate=1.0, seed=0)
-    tabs = np.zeros((n_req, 10, 2000))
+    slot, by_l = {}, {}  # each request's table of lmax + 1 channels, one handle per lmax
+    for k, r in enumerate(reqs):
+        slot[k] = (r.lmax, len(by_l.setdefault(r.lmax, [])))
+        by_l[r.lmax].append(workloads.radial_table(np.random.default_rng(r.seed), r.lmax, 2000, 3.0))
     gen = torch.Generator(device=dev)
     gen.manual_seed(7)
     pts = []
     for k, r in enumerate(reqs):
-        tabs[k, : r.lmax + 1] = workloads.radial_table(np.random.default_rng(r.seed), r.lmax, 2000, 3.0)
         d = torch.randn((r.n, 3), generator=gen, dtype=torch.float64, device=dev)
         d = d / d.norm(dim=1, keepdim=True)
         rr = 3.0 * torch.rand((r.n, 1), generator=gen, dtype=torch.float64, device=dev) ** (1 / 3)
         dt = torch.float64 if r.dtype == "f64" else torch.float32
         pts.append((torch.from_numpy(r.center).to(dev) + d * rr).to(dt).contiguous())
     _say("case: full serving workload,", n_req, "requests,", sum(r.n for r in reqs), "points")
-    radial = sh.Radial(tabs, 3.0)
+    radials = {l: sh.Radial(np.stack(t), 3.0) for l, t in by_l.items()}
     srv = Server(64 << 30, max_pending=n_req + 1, n_slots=3)
-    atoms = [srv.add_atom(p, r.center, radial, table=k) for k, (p, r) in enumerate(zip(pts, reqs))]
+    atoms = [srv.add_atom(p, r.center, radials[slot[k][0]], table=slot[k][1]) for k, (p, r) in enumerate(zip(pts, reqs))]
     rng = np.random.default_rng(5)
     sample = set(int(k) for k in rng.choice(n_req, 16, replace=False))
     tickets = {}
@@ -274,10 +276,11 @@ def test_full_workload_sampled(dev, orc):
         got = srv.result(t, r.lmax, r.n, dt)[:, it].double().cpu().numpy()
         p = pts[k][it].double().cpu().numpy()
         ref = orc.projectors(r.lmax, np.asarray(r.center)[None], np.array([0, idx.size]), p,
-                             tabs[k: k + 1, : r.lmax + 1], 3.0)
+                             by_l[r.lmax][slot[k][1]][None], 3.0)
         F = (r.lmax + 1) ** 2
         err = float(np.abs(got.astype(LD) - ref.reshape(F, idx.size)).max())
         assert err <= (1e-13 if r.dtype == "f64" else 5e-6), (k, r.lmax, r.dtype, err)
         srv.release(t)
     srv.close()
-    radial.close()
+    for rad in radials.values():
+        rad.close()
