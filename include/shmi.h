@@ -236,8 +236,10 @@ int sh_projectors_f32(int lmax, int n_atoms, const float *centers, const int64_t
  * one batch and launches it on a free stream slot (one kernel per (dtype, lmax)
  * group of the batch), so requests that arrive while others run are admitted as
  * memory and slots free up and their work overlaps on the device.  Results stay
- * on the device until released.  A request's latency is measured from
- * sh_server_submit to the host seeing its batch complete.  Creation also runs
+ * on the device until released.  Within a batch the groups run smallest output
+ * first and each request completes when its group does.  A request's latency is
+ * measured from sh_server_submit to the host seeing its group complete.  Creation
+ * also runs
  * every serving kernel once on an empty request, so that no first launch (which
  * is slow) falls in the middle of serving.  Every function is thread-safe.
  */

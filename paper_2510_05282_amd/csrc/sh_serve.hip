@@ -6,7 +6,9 @@
 // it (registers and occupancy sized for that lmax, no per-point dispatch); each
 // request is cut into tiles of 256 lanes x PPL adjacent points, evaluated with the
 // same projector code as sh_projectors (PPL as there: the vector width for a group
-// of at least kProjVecPoints points, else 1).  Request descriptors and their
+// of at least kProjVecPoints points, else 1).  The groups are launched smallest
+// output first, each followed by an event, and progress() reports a group's
+// requests as soon as its event completes.  Request descriptors and their
 // first-tile indices travel host -> device in one copy through a pinned staging
 // buffer per slot (the slot is reused only after its previous batch has completed,
 // so the staging buffer is never overwritten in flight).
@@ -126,7 +128,11 @@ public:
             return;
         }
         for (Slot& s : slots_) {
-            if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||
+            s.group_done.assign(kMaxGroups, nullptr);
+            bool events_ok = true;
+            for (hipEvent_t& ev : s.group_done)
+                events_ok = events_ok && hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess;
+            if (!events_ok || hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||
                 hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess ||
                 hipHostMalloc(reinterpret_cast<void**>(&s.host), kSlotBytes) != hipSuccess ||
                 hipMalloc(&s.dev, kSlotBytes) != hipSuccess) {
@@ -147,6 +153,8 @@ public:
             if (s.dev) (void)hipFree(s.dev);
             if (s.host) (void)hipHostFree(s.host);
             if (s.done) (void)hipEventDestroy(s.done);
+            for (hipEvent_t ev : s.group_done)
+                if (ev) (void)hipEventDestroy(ev);
             if (s.stream) (void)hipStreamDestroy(s.stream);
         }
         if (arena_) (void)hipFree(arena_);
@@ -174,12 +182,14 @@ public:
         groups_.clear();
         for (size_t k = 0; k < n; ++k) {
             if (groups_.empty() || key(order_[k]) != key(order_[groups_.back().first]))
-                groups_.push_back({int(k), 0, 1});
+                groups_.push_back({int(k), 0, 0, 1});
             groups_.back().tiles += items[order_[k]].atom.n;  // points, until turned into tiles below
         }
         for (Group& g : groups_) {
-            const bool f64 = items[order_[g.first]].atom.dtype == SH_F64;
+            const Item& it = items[order_[g.first]];
+            const bool f64 = it.atom.dtype == SH_F64;
             g.ppl = g.tiles >= shk::kProjVecPoints ? (f64 ? shk::kProjPpl<double> : shk::kProjPpl<float>) : 1;
+            g.bytes = g.tiles * (it.lmax + 1) * (it.lmax + 1) * (f64 ? 8 : 4);  // output bytes
             g.tiles = 0;
         }
         // descriptors, then their first-tile indices (relative to their group), in one copy
@@ -214,7 +224,17 @@ public:
         hipError_t e = hipMemcpyAsync(s.dev, s.host, (sizeof(shk::ServeDesc) + sizeof(int64_t)) * n,
                                       hipMemcpyHostToDevice, s.stream);
         const int64_t* dev_tile0 = reinterpret_cast<const int64_t*>(s.dev + n);
-        for (size_t gi = 0; gi < groups_.size() && e == hipSuccess; ++gi) {
+        // smallest output first, each group's completion recorded, so the requests of
+        // small groups complete without waiting for the large ones of the batch
+        launch_order_.resize(groups_.size());
+        for (size_t gi = 0; gi < groups_.size(); ++gi) launch_order_[gi] = int(gi);
+        std::stable_sort(launch_order_.begin(), launch_order_.end(),
+                         [&](int a, int b) { return groups_[a].bytes < groups_[b].bytes; });
+        s.group_items.clear();
+        s.group_end.clear();
+        s.next = 0;
+        for (size_t q = 0; q < launch_order_.size() && e == hipSuccess; ++q) {
+            const size_t gi = size_t(launch_order_[q]);
             const Group& g = groups_[gi];
             const int b = g.first;
             const int m = (gi + 1 < groups_.size() ? groups_[gi + 1].first : int(n)) - b;
@@ -222,6 +242,9 @@ public:
             e = d.dtype == SH_F64
                     ? shk::launch_group<double>(d.lmax, g.ppl, g.tiles, s.dev + b, dev_tile0 + b, m, s.stream)
                     : shk::launch_group<float>(d.lmax, g.ppl, g.tiles, s.dev + b, dev_tile0 + b, m, s.stream);
+            if (e == hipSuccess) e = hipEventRecord(s.group_done[q], s.stream);
+            for (int k = b; k < b + m; ++k) s.group_items.push_back(order_[k]);
+            s.group_end.push_back(int(s.group_items.size()));
         }
         if (e == hipSuccess) e = hipEventRecord(s.done, s.stream);
         if (e != hipSuccess) {
@@ -241,13 +264,34 @@ public:
         return -1;
     }
 
+    // the groups launched so far complete in launch order (one stream)
+    int progress(int slot, std::vector<int>& done) override
+    {
+        Slot& s = slots_[slot];
+        while (s.next < int(s.group_end.size())) {
+            const hipError_t e = hipEventQuery(s.group_done[s.next]);
+            if (e == hipErrorNotReady) return 0;
+            if (e != hipSuccess) return -1;
+            for (int i = s.next ? s.group_end[s.next - 1] : 0; i < s.group_end[s.next]; ++i)
+                done.push_back(s.group_items[i]);
+            ++s.next;
+        }
+        return query(slot);
+    }
+
 private:
     static constexpr int64_t kMaxItems = 8192;
     // per slot: up to kMaxItems descriptors followed by as many first-tile indices
     static constexpr size_t kSlotBytes = (sizeof(shk::ServeDesc) + sizeof(int64_t)) * kMaxItems;
+    // one launch per (dtype, lmax) group
+    static constexpr int kMaxGroups = 2 * (SH_LMAX + 1);
     struct Slot {
         hipStream_t stream = nullptr;
         hipEvent_t done = nullptr;
+        std::vector<hipEvent_t> group_done;  // recorded after each launch of a batch, in launch order
+        std::vector<int> group_items;        // the batch's item indices, group by group in launch order
+        std::vector<int> group_end;          // end of each group's items in group_items
+        int next = 0;                        // first group not yet reported complete
         shk::ServeDesc* host = nullptr;
         shk::ServeDesc* dev = nullptr;
     };
@@ -277,8 +321,10 @@ private:
     struct Group {
         int first;      // first item (in order_)
         int64_t tiles;  // tiles of the group's launch
+        int64_t bytes;  // output bytes
         int ppl;        // points per lane
     };
+    std::vector<int> launch_order_;  // launch() scratch: groups, smallest output first
     std::vector<Group> groups_;  // launch() scratch
 };
 

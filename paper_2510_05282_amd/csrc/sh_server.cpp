@@ -69,6 +69,7 @@ Server::Server(std::unique_ptr<Executor> ex, uint64_t budget, int64_t max_pendin
 {
     const int ns = ex_->n_slots();
     slot_reqs_.resize(ns);
+    finished_.resize(ns);
     for (int s = ns - 1; s >= 0; --s) free_slots_.push_back(s);
     st_.first_submit_s = -1.0;
     thr_ = std::thread([this] { loop(); });
@@ -148,39 +149,71 @@ bool Server::admit_locked()
     return prog;
 }
 
+void Server::finish_req_locked(int64_t t, int status, Clock::time_point now)
+{
+    Request& r = reqs_[t];
+    r.t_done = now;
+    if (status == SH_OK) {
+        r.state = kDone;
+        st_.completed++;
+        st_.points_done += atoms_[r.atom].n;
+        lat_ms_.push_back(secs(r.t_done - r.t_submit) * 1e3);
+        st_.last_done_s = secs(now - t0_);
+        if (r.flags & SH_REQ_AUTORELEASE) {
+            arena_.release(r.offset, r.bytes);
+            r.state = kReleased;
+        }
+    } else {
+        r.state = kFailed;
+        r.error = status;
+        st_.failed++;
+        arena_.release(r.offset, r.bytes);
+    }
+}
+
 void Server::finish_locked(int slot, int status)
 {
     const Clock::time_point now = Clock::now();
-    for (int64_t t : slot_reqs_[slot]) {
-        Request& r = reqs_[t];
-        r.t_done = now;
-        if (status == SH_OK) {
-            r.state = kDone;
-            st_.completed++;
-            st_.points_done += atoms_[r.atom].n;
-            lat_ms_.push_back(secs(r.t_done - r.t_submit) * 1e3);
-            st_.last_done_s = secs(now - t0_);
-            if (r.flags & SH_REQ_AUTORELEASE) {
-                arena_.release(r.offset, r.bytes);
-                r.state = kReleased;
-            }
-        } else {
-            r.state = kFailed;
-            r.error = status;
-            st_.failed++;
-            arena_.release(r.offset, r.bytes);
-        }
-    }
+    for (size_t i = 0; i < slot_reqs_[slot].size(); ++i)
+        if (!finished_[slot][i]) finish_req_locked(slot_reqs_[slot][i], status, now);
     st_.bytes_in_use = arena_.in_use();
     slot_reqs_[slot].clear();
+    finished_[slot].clear();
     free_slots_.push_back(slot);
     cv_done_.notify_all();
 }
 
-// Finishes the batches that have completed.  Called with lk held; the completion
-// queries (HIP runtime calls) run with it released, so submitters are not held up
-// by them.  Only the scheduler thread launches, queries and finishes slots, so the
-// busy set cannot change while the lock is released.
+// Finishes what progress() reported for the busy slots (done_, early_): single
+// requests whose results are complete, and whole batches that ended.  lk held.
+bool Server::apply_locked()
+{
+    bool prog = false, early = false;
+    const Clock::time_point now = Clock::now();
+    for (size_t k = 0; k < busy_.size(); ++k) {
+        const int slot = busy_[k];
+        for (int i : early_[k]) {
+            if (i < 0 || i >= int(finished_[slot].size()) || finished_[slot][i]) continue;
+            finished_[slot][i] = 1;
+            finish_req_locked(slot_reqs_[slot][i], SH_OK, now);
+            early = true;
+        }
+        early_[k].clear();
+        if (done_[k] != 0) {
+            busy_slots_--;
+            finish_locked(slot, done_[k] > 0 ? SH_OK : SH_EHIP);
+            prog = true;
+        }
+    }
+    if (early) {
+        st_.bytes_in_use = arena_.in_use();
+        cv_done_.notify_all();
+    }
+    return prog || early;
+}
+
+// Finishes the requests and batches that have completed.  Called with lk held;
+// the completion queries (HIP runtime calls) run with it released, so submitters
+// are not held up.
 bool Server::reap(std::unique_lock<std::mutex>& lk)
 {
     busy_.clear();
@@ -188,17 +221,12 @@ bool Server::reap(std::unique_lock<std::mutex>& lk)
         if (!slot_reqs_[s].empty()) busy_.push_back(s);
     if (busy_.empty()) return false;
     done_.assign(busy_.size(), 0);
+    early_.resize(busy_.size());
+    for (auto& e : early_) e.clear();
     lk.unlock();
-    for (size_t k = 0; k < busy_.size(); ++k) done_[k] = ex_->query(busy_[k]);
+    for (size_t k = 0; k < busy_.size(); ++k) done_[k] = ex_->progress(busy_[k], early_[k]);
     lk.lock();
-    bool prog = false;
-    for (size_t k = 0; k < busy_.size(); ++k) {
-        if (done_[k] == 0) continue;
-        busy_slots_--;
-        finish_locked(busy_[k], done_[k] > 0 ? SH_OK : SH_EHIP);
-        prog = true;
-    }
-    return prog;
+    return apply_locked();
 }
 
 void Server::loop()
@@ -240,6 +268,7 @@ void Server::loop()
                 r.state = kRunning;
                 slot_reqs_[slot].push_back(queued_[k]);
             }
+            finished_[slot].assign(slot_reqs_[slot].size(), 0);
             queued_.erase(queued_.begin(), queued_.begin() + k);
             // the slot counts as busy before the lock is dropped, so drain() cannot
             // observe an empty server while this batch is being launched
@@ -265,12 +294,19 @@ void Server::loop()
                 // busy_ and free_slots_ change only on this thread.
                 const uint64_t g = gen_;
                 const bool slot_free = !free_slots_.empty();
+                done_.assign(busy_.size(), 0);
+                early_.resize(busy_.size());
+                for (auto& e : early_) e.clear();
                 lk.unlock();
-                for (bool done = false; !done && !(gen_ != g && (slot_free || stop_));) {
+                for (bool got = false; !got && !(gen_ != g && (slot_free || stop_));) {
                     std::this_thread::yield();
-                    for (int s : busy_) done = done || ex_->query(s) != 0;
+                    for (size_t k = 0; k < busy_.size(); ++k) {
+                        if (done_[k] == 0) done_[k] = ex_->progress(busy_[k], early_[k]);
+                        got = got || done_[k] != 0 || !early_[k].empty();
+                    }
                 }
                 lk.lock();
+                apply_locked();
             } else {
                 // nothing runs and nothing can be admitted: watch for a submit, a
                 // release or shutdown with the lock free for up to kIdleSpin (a
@@ -371,7 +407,8 @@ namespace {
 class SimExecutor final : public Executor {
 public:
     SimExecutor(int n_slots, double bps, int fail_every, double launch_s)
-        : done_at_(n_slots), fail_(n_slots, false), bps_(bps), fail_every_(fail_every), launch_s_(launch_s)
+        : item_done_(n_slots), next_(n_slots, 0), done_at_(n_slots), fail_(n_slots, false), bps_(bps),
+          fail_every_(fail_every), launch_s_(launch_s)
     {
     }
     int n_slots() const override { return int(done_at_.size()); }
@@ -379,13 +416,27 @@ public:
     int64_t max_tiles() const override { return int64_t(1) << 22; }
     int64_t tile_points() const override { return 256; }
     void* arena_base() override { return nullptr; }
+    // Items run one after another, smallest output first (as the HIP executor orders
+    // its launches); each completes when its cumulative bytes have been written.
     int launch(int slot, const std::vector<Item>& items) override
     {
         if (launch_s_ > 0) std::this_thread::sleep_for(std::chrono::duration<double>(launch_s_));
+        const Clock::time_point t0 = Clock::now();
+        auto& q = item_done_[slot];
+        q.clear();
+        std::vector<int> idx(items.size());
+        for (size_t k = 0; k < idx.size(); ++k) idx[k] = int(k);
+        std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+            return out_bytes(items[a].atom, items[a].lmax) < out_bytes(items[b].atom, items[b].lmax);
+        });
         double bytes = 0;
-        for (const Item& it : items) bytes += double(out_bytes(it.atom, it.lmax));
-        done_at_[slot] = Clock::now() + std::chrono::duration_cast<Clock::duration>(
-                                            std::chrono::duration<double>(bytes / bps_));
+        for (int k : idx) {
+            bytes += double(out_bytes(items[k].atom, items[k].lmax));
+            q.push_back({t0 + std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(bytes / bps_)),
+                         k});
+        }
+        done_at_[slot] = t0 + std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(bytes / bps_));
+        next_[slot] = 0;
         ++launches_;
         fail_[slot] = fail_every_ > 0 && launches_ % fail_every_ == 0;
         return SH_OK;
@@ -395,8 +446,19 @@ public:
         if (Clock::now() < done_at_[slot]) return 0;
         return fail_[slot] ? -1 : 1;
     }
+    // a failing batch reports nothing early: all its requests fail with it
+    int progress(int slot, std::vector<int>& done) override
+    {
+        const Clock::time_point now = Clock::now();
+        const auto& q = item_done_[slot];
+        while (!fail_[slot] && next_[slot] < q.size() && q[next_[slot]].first <= now)
+            done.push_back(q[next_[slot]++].second);
+        return query(slot);
+    }
 
 private:
+    std::vector<std::vector<std::pair<Clock::time_point, int>>> item_done_;  // per slot: (completion, item)
+    std::vector<size_t> next_;  // per slot: first item not yet reported
     std::vector<Clock::time_point> done_at_;
     std::vector<bool> fail_;
     double bps_;

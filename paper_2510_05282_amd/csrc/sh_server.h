@@ -63,6 +63,15 @@ public:
     virtual int launch(int slot, const std::vector<Item>& items) = 0;
     // 1: the slot's batch finished; 0: still running; negative: it failed.
     virtual int query(int slot) = 0;
+    // Items of the slot's batch (indices into the vector launch() was given) whose
+    // results are complete and were not reported before are appended to `done`;
+    // returns what query() returns.  The default reports no item early: every item
+    // completes with its batch.
+    virtual int progress(int slot, std::vector<int>& done)
+    {
+        (void)done;
+        return query(slot);
+    }
 };
 
 // First-fit allocator over [0, capacity) with coalescing, 256-byte granularity.
@@ -123,6 +132,8 @@ private:
     bool reap(std::unique_lock<std::mutex>& lk);
     bool admit_locked();
     void finish_locked(int slot, int status);
+    void finish_req_locked(int64_t ticket, int status, Clock::time_point now);
+    bool apply_locked();
 
     std::unique_ptr<Executor> ex_;
     Arena arena_;
@@ -141,7 +152,9 @@ private:
     std::atomic<uint64_t> gen_{0};  // bumped by every submit, release and shutdown
     // how long an idle scheduler watches gen_ before it sleeps on cv_work_
     static constexpr std::chrono::microseconds kIdleSpin{200};
-    std::vector<int> busy_, done_;  // scratch of reap(): busy slots and their query results
+    std::vector<int> busy_, done_;  // scratch of reap(): busy slots and their progress() results
+    std::vector<std::vector<int>> early_;    // scratch of reap(): items reported complete per busy slot
+    std::vector<std::vector<char>> finished_;  // per slot: which of its requests are already finished
     std::vector<double> lat_ms_;
     Stats st_{};
     Clock::time_point t0_;

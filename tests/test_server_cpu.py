@@ -133,6 +133,29 @@ def test_latency_includes_batch_time():
     s.close()
 
 
+def test_small_request_completes_before_large_one_of_its_batch():
+    """Requests complete as their part of a batch does, smallest output first: with
+    one slot, a large (80 MB) and a small (8 KB) request queued behind a 20 MB one
+    share the second batch; the small one completes right after the first batch,
+    the large one 80 ms later."""
+    rate = 1e9
+    s = _server(1 << 30, n_slots=1, sim_bytes_per_s=rate)
+    blocker = s.add_atom(FAKE, [0, 0, 0], dtype=SH_F64, n=25000)  # lmax 9: 20 MB -> 20 ms
+    big = s.add_atom(FAKE, [0, 0, 0], dtype=SH_F64, n=100000)     # lmax 9: 80 MB -> 80 ms
+    small = s.add_atom(FAKE, [0, 0, 0], dtype=SH_F64, n=1000)     # lmax 0: 8 KB
+    s.submit(blocker, 9, SH_REQ_AUTORELEASE)
+    time.sleep(2e-3)  # the first batch is running
+    s.submit(big, 9, SH_REQ_AUTORELEASE)
+    s.submit(small, 0, SH_REQ_AUTORELEASE)
+    s.drain(10)
+    st = s.stats()
+    assert st["completed"] == 3 and st["batches"] == 2, st
+    lat = s.latencies_ms()  # completion order: blocker, small, big
+    assert lat[1] < 40.0, lat
+    assert lat[2] >= 80.0 * 0.99, lat
+    s.close()
+
+
 def test_drain_waits_for_batches_being_launched():
     """Regression: drain() must not return while the scheduler is launching a batch
     (a launch takes host time; the slot counts as busy from before it starts)."""
