@@ -8,7 +8,8 @@ import time
 import pytest
 
 from paper_2510_05282_amd import _lib
-from paper_2510_05282_amd.serve import DONE, FAILED, PENDING, RELEASED, SH_F32, SH_F64, SH_REQ_AUTORELEASE, Server
+from paper_2510_05282_amd.serve import (DONE, FAILED, PENDING, RELEASED, RUNNING, SH_F32, SH_F64, SH_REQ_AUTORELEASE,
+                                        Server)
 
 FAKE = 0x10000  # simulated atoms need a nonzero point address; it is never dereferenced
 
@@ -143,8 +144,11 @@ def test_small_request_completes_before_large_one_of_its_batch():
     blocker = s.add_atom(FAKE, [0, 0, 0], dtype=SH_F64, n=25000)  # lmax 9: 20 MB -> 20 ms
     big = s.add_atom(FAKE, [0, 0, 0], dtype=SH_F64, n=100000)     # lmax 9: 80 MB -> 80 ms
     small = s.add_atom(FAKE, [0, 0, 0], dtype=SH_F64, n=1000)     # lmax 0: 8 KB
-    s.submit(blocker, 9, SH_REQ_AUTORELEASE)
-    time.sleep(2e-3)  # the first batch is running
+    t0 = s.submit(blocker, 9, SH_REQ_AUTORELEASE)
+    deadline = time.monotonic() + 5.0
+    while s.poll(t0) != RUNNING:  # the first batch is running
+        assert time.monotonic() < deadline
+        time.sleep(1e-4)
     s.submit(big, 9, SH_REQ_AUTORELEASE)
     s.submit(small, 0, SH_REQ_AUTORELEASE)
     s.drain(10)
