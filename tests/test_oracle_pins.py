@@ -383,6 +383,97 @@ def test_spinor_harmonics_closed_forms(orc):
     assert np.abs(G - np.eye(r2.shape[0])).max() <= 1e-13
 
 
+def _spinor_cx(orc, lmax, theta, phi):
+    re, im = orc.eval_spinor_angles(lmax, np.asarray(theta, dtype=LD), np.asarray(phi, dtype=LD))
+    return re + 1j * im  # [spinor][2][n] complex long double
+
+
+def test_spinor_labels_are_angular_momentum_eigenstates(orc):
+    """The (l, j, m_j) label of every spinor of the oracle, pinned by the angular
+    momentum algebra rather than by eq. spinorial itself: with L_z = -i d/dphi and
+    L_+- = e^{+-i phi} (+-d/dtheta + i cot(theta) d/dphi) (Condon-Shortley
+    convention) applied by 4th-order central differences,
+        J_z Omega = (L_z + sigma_z / 2) Omega = m_j Omega,
+        (sigma . L) Omega = (j(j+1) - l(l+1) - 3/4) Omega = l (j = l + 1/2), -(l+1) (j = l - 1/2),
+    where (sigma . L) Omega = (L_z up + L_- down, -L_z down + L_+ up).  A reversed
+    m_j order, swapped j = l +- 1/2 blocks or a wrong relative sign between the two
+    components fails one of them."""
+    lmax = 4
+    rng = np.random.default_rng(93)
+    th = rng.uniform(0.3, 2.8, 24).astype(LD)
+    ph = rng.uniform(0.0, 2 * np.pi, 24).astype(LD)
+    h = LD("1e-3")
+    O = _spinor_cx(orc, lmax, th, ph)
+
+    def d4(f, a, b):  # 4th-order central difference in the angle selected by (a, b)
+        return (-f(2 * a, 2 * b) + 8 * f(a, b) - 8 * f(-a, -b) + f(-2 * a, -2 * b)) / (12 * h)
+
+    dth = d4(lambda a, b: _spinor_cx(orc, lmax, th + a, ph + b), h, LD(0))
+    dph = d4(lambda a, b: _spinor_cx(orc, lmax, th + a, ph + b), LD(0), h)
+    cot = np.cos(th) / np.sin(th)
+    Lz = -1j * dph
+    Lp = np.exp(1j * ph) * (dth + 1j * cot * dph)
+    Lm = np.exp(-1j * ph) * (-dth + 1j * cot * dph)
+    up, dn = 0, 1
+    checked = 0
+    for l in range(lmax + 1):
+        for kappa in (-1, 1):
+            if kappa < 0 and l == 0:
+                continue
+            j2 = 2 * l + kappa
+            so = l if kappa > 0 else -(l + 1)
+            for mj2 in range(-j2, j2 + 1, 2):
+                k = orc.spinor_index(l, kappa, mj2)
+                jz = np.stack([Lz[k, up] + O[k, up] / 2, Lz[k, dn] - O[k, dn] / 2])
+                sl = np.stack([Lz[k, up] + Lm[k, dn], -Lz[k, dn] + Lp[k, up]])
+                scale = 1 + np.abs(O[k]).max()
+                assert np.abs(jz - LD(mj2) / 2 * O[k]).max() <= 1e-9 * scale, (l, kappa, mj2)
+                assert np.abs(sl - so * O[k]).max() <= 1e-9 * scale, (l, kappa, mj2)
+                checked += 1
+    assert checked == 2 * (lmax + 1) ** 2
+
+
+def test_spinor_azimuthal_rotation_and_mpmath(orc):
+    """phi -> phi + alpha multiplies the upper component of Omega_{j m_j} by
+    e^{i (m_j - 1/2) alpha} and the lower by e^{i (m_j + 1/2) alpha}; and every
+    spinor for l = 1 .. 4 equals eq. spinorial composed from mpmath's spherharm at
+    40 digits (j = l + 1/2: upper +sqrt(l + m_j + 1/2), lower sqrt(l - m_j + 1/2);
+    j = l - 1/2: upper -sqrt(l - m_j + 1/2), lower sqrt(l + m_j + 1/2); all over
+    sqrt(2l + 1), upper with Y_l^{m_j - 1/2}, lower with Y_l^{m_j + 1/2})."""
+    lmax = 4
+    rng = np.random.default_rng(94)
+    th = rng.uniform(0.05, 3.09, 12).astype(LD)
+    ph = rng.uniform(0.0, 2 * np.pi, 12).astype(LD)
+    alpha = LD("0.7345")
+    O = _spinor_cx(orc, lmax, th, ph)
+    R = _spinor_cx(orc, lmax, th, ph + alpha)
+    mp.mp.dps = 40
+    for l in range(1, lmax + 1):
+        for kappa in (-1, 1):
+            j2 = 2 * l + kappa
+            for mj2 in range(-j2, j2 + 1, 2):
+                k = orc.spinor_index(l, kappa, mj2)
+                for c, shift in ((0, -1), (1, 1)):
+                    ph_fac = np.exp(1j * alpha * LD(mj2 + shift) / 2)
+                    assert np.abs(R[k, c] - ph_fac * O[k, c]).max() <= 1e-15, (l, kappa, mj2, c)
+                for i in range(th.size):
+                    t, f = _mpf(th[i]), _mpf(ph[i])
+
+                    def Y(m):
+                        return mp.mpc(0) if abs(m) > l else mp.spherharm(l, m, t, f)
+
+                    mu, ml = (mj2 - 1) // 2, (mj2 + 1) // 2
+                    if kappa > 0:
+                        cu, cl = mp.sqrt(mp.mpf(2 * l + mj2 + 1) / 2), mp.sqrt(mp.mpf(2 * l - mj2 + 1) / 2)
+                    else:
+                        cu, cl = -mp.sqrt(mp.mpf(2 * l - mj2 + 1) / 2), mp.sqrt(mp.mpf(2 * l + mj2 + 1) / 2)
+                    den = mp.sqrt(2 * l + 1)
+                    for c, ref in ((0, cu * Y(mu) / den), (1, cl * Y(ml) / den)):
+                        got = O[k, c, i]
+                        err = abs(mp.mpc(_mpf(got.real), _mpf(got.imag)) - ref)
+                        assert err <= 1e-17, (l, kappa, mj2, c, float(err))
+
+
 def test_library_routine_std_sph_legendre(orc, tmp_path):
     """libstdc++'s std::sph_legendre(l, m, theta) = Y_l^m(theta, 0), Condon-Shortley
     phase included, so R_l^0 = Y_l^0 and R_l^{+-m} = sqrt(2) (-1)^m Y_l^m(theta, 0)
