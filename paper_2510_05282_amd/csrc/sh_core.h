@@ -79,6 +79,26 @@ template <> struct K<float> {
 template <typename A, typename B>
 __host__ __device__ __forceinline__ auto pf(A a, B b) { return (a - b) * (a + b); }
 
+// p(c x, y) with each root factor c x -+ y one fused multiply-add.  The library is
+// compiled with contraction only where the source writes it (-ffp-contract=on),
+// so a point's value is the same whether it is evaluated alone or as a lane of a
+// vector of adjacent points.
+// (Other arithmetic types, such as the dual numbers of the backward pass, take
+// the plain product.)
+template <typename T> struct fma_lanes : std::is_floating_point<T> {};
+template <typename S, int N> struct fma_lanes<S __attribute__((ext_vector_type(N)))> : std::true_type {};
+
+template <typename T>
+__host__ __device__ __forceinline__ T pfs(scalar_t<T> c, T x, T y)
+{
+    if constexpr (fma_lanes<T>::value) {
+        const T cv = T(c);
+        return __builtin_elementwise_fma(cv, x, -y) * __builtin_elementwise_fma(cv, x, y);
+    } else {
+        return pf(c * x, y);
+    }
+}
+
 // Shat_m(x, y) = y * x^[m even] * prod_{k=1}^{ceil(m/2)-1} p(tan(k pi/m) x, y).
 template <typename T, int M>
 __host__ __device__ __forceinline__ T shat(T x, T y)
@@ -87,7 +107,7 @@ __host__ __device__ __forceinline__ T shat(T x, T y)
     if constexpr (M % 2 == 0) acc *= x;
     static_for<0, (M + 1) / 2 - 1>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
-        acc *= pf(K<scalar_t<T>>::tans(M, k) * x, y);
+        acc *= pfs<T>(K<scalar_t<T>>::tans(M, k), x, y);
     });
     return acc;
 }
@@ -100,7 +120,7 @@ __host__ __device__ __forceinline__ T chat(T x, T y)
     if constexpr (M % 2 == 1) acc = x;
     static_for<0, M / 2>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
-        const T f = pf(K<scalar_t<T>>::tanc(M, k) * x, y);
+        const T f = pfs<T>(K<scalar_t<T>>::tanc(M, k), x, y);
         if constexpr (k == 0 && M % 2 == 0) acc = f;
         else acc *= f;
     });

@@ -1,0 +1,106 @@
+"""A point's values do not depend on where it sits in a batch.
+
+The kernels evaluate several adjacent points per lane as one vector (two FP64 or
+four FP32) where a launch allows it, and single points elsewhere (a batch's last
+odd points, rows that are not 16-byte aligned, launches below the vector size of
+the projector and serving kernels).  The library is compiled so that a multiply
+and an add are fused only where the source says so, which makes the vector and
+the scalar code the same sequence of IEEE operations per point: the results are
+compared bit for bit here, at the sizes where the lane width changes."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2510_05282_amd as sh
+from paper_2510_05282_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _pts(n, seed, dtype, dev):
+    p = np.concatenate([workloads.points_plain_eval(seed=seed, n_random=n - 64)])
+    return torch.from_numpy(p).to(dev, dtype).contiguous()
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_real_harmonics_vector_and_single_lanes(dev, dtype):
+    """n = 4k + 1 points: the main launch takes 16 bytes of points per lane and the
+    last point goes through the one-point launch; an output with an odd row stride
+    sends every point through the one-point launch; the batch without its first
+    point is a whole number of vectors.  All three agree bit for bit."""
+    n = 40001
+    x = _pts(n, 1, dtype, dev)
+    fn = sh.sh_eval if dtype == torch.float64 else sh.sh_eval_f32
+    for lmax in (2, 6, 9):
+        F = (lmax + 1) ** 2
+        _say("case: lane identity, real, lmax", lmax, dtype)
+        y = fn(lmax, x)
+        wide = torch.empty((F, n + 2), dtype=dtype, device=dev)  # odd row stride
+        one = sh.sh_eval_ld(lmax, x, wide[:, :n])
+        assert torch.equal(y, one)
+        assert torch.equal(y[:, 1:], fn(lmax, x[1:].contiguous()))
+
+
+def test_other_kernels_vector_and_single_lanes(dev):
+    """The same for the kernels with two FP64 / four FP32 points per lane and a
+    one-point tail: complex (FP32), recurrence, and the backward passes."""
+    n = 20001
+    for dtype in (torch.float64, torch.float32):
+        x = _pts(n, 2, dtype, dev)
+        xs = x[1:].contiguous()
+        f32 = dtype == torch.float32
+        cases = [("rec lmax 12", lambda a: (sh.sh_eval_rec_f32 if f32 else sh.sh_eval_rec)(12, a))]
+        if f32:
+            cases.append(("complex lmax 9", lambda a: sh.sh_eval_complex_f32(9, a)))
+        for name, f in cases:
+            _say("case: lane identity,", name, dtype)
+            assert torch.equal(f(x)[..., 1:], f(xs)), name
+        for lmax, fn in ((6, sh.sh_eval_grad_f32 if f32 else sh.sh_eval_grad),
+                         (14, sh.sh_eval_grad_rec_f32 if f32 else sh.sh_eval_grad_rec)):
+            F = (lmax + 1) ** 2
+            gen = torch.Generator(device=dev)
+            gen.manual_seed(lmax)
+            G = torch.randn((F, n), generator=gen, dtype=dtype, device=dev)
+            _say("case: lane identity, backward lmax", lmax, dtype)
+            assert torch.equal(fn(lmax, x, G)[1:], fn(lmax, xs, G[:, 1:].contiguous()))
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+def test_projector_build_vector_and_single_lanes(dev, dt):
+    """Nine atoms of 120,001 to 120,009 points: together they take the launch with
+    several adjacent points per lane (more than 2^20 points; the odd sizes make
+    lanes straddle atom boundaries), each alone the one-point launch.  Every
+    atom's block is the same bit for bit."""
+    rng = np.random.default_rng(21)
+    sizes = [120_001 + k for k in range(9)]
+    assert sum(sizes) >= 1 << 20
+    tabs = np.stack([workloads.radial_table(rng, 5, 2000, 3.0) for _ in sizes])
+    radial = sh.Radial(tabs, 3.0)
+    cen = rng.uniform(0.0, 10.0, size=(len(sizes), 3))
+    pts = np.concatenate([c + rng.uniform(-1.7, 1.7, size=(k, 3)) for c, k in zip(cen, sizes)])
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    fn = sh.sh_projectors if dt == torch.float64 else sh.sh_projectors_f32
+    c_d, p_d = torch.from_numpy(cen).to(dev, dt), torch.from_numpy(pts).to(dev, dt)
+    _say("case: projector lane identity,", sum(sizes), "points,", dt)
+    lmax = 5
+    F = (lmax + 1) ** 2
+    allb = fn(lmax, c_d, torch.from_numpy(off).to(dev), p_d, radial)
+    for a, k in enumerate(sizes):
+        toa = torch.tensor([a], dtype=torch.int32, device=dev)
+        one = fn(lmax, c_d[a:a + 1].contiguous(), torch.tensor([0, k], dtype=torch.int64, device=dev),
+                 p_d[off[a]:off[a + 1]].contiguous(), radial, table_of_atom=toa)
+        assert torch.equal(allb[F * off[a]:F * off[a + 1]], one), a
+    radial.close()

@@ -1,5 +1,5 @@
 """The projector server on the GPU: every request's result is the same alone and
-in a mixed stream (same kernel code for its lmax and dtype: bitwise), and
+in a mixed stream (bit for bit, also where the lane width changes), and
 matches the oracle."""
 from __future__ import annotations
 
@@ -193,23 +193,33 @@ def test_tiny_and_odd_requests_match_projectors(dev):
     radial.close()
 
 
+def _alone(dev, lmax, center, points, radial, table):
+    """sh_projectors (or its FP32 twin) of one atom, in the atom's dtype."""
+    dt = points.dtype
+    fn = sh.sh_projectors if dt == torch.float64 else sh.sh_projectors_f32
+    return fn(lmax, torch.tensor(np.asarray(center)[None], dtype=dt, device=dev),
+              torch.tensor([0, points.shape[0]], dtype=torch.int64, device=dev), points, radial,
+              table_of_atom=torch.tensor([table], dtype=torch.int32, device=dev))
+
+
 @pytest.mark.parametrize("dt", ["f64", "f32"])
 def test_tiny_requests_in_a_large_group(dev, dt):
     """Requests of 1 to 7 points batched with one of 2^20 + 7 points of the same
     (dtype, lmax): the group is large enough for the launch with several adjacent
-    points per lane, so the tiny requests are single partial lanes of it.  Against
-    sh_projectors on each atom alone."""
+    points per lane, so the tiny requests are single partial lanes of it.  Bit for
+    bit against sh_projectors on each atom alone (the one-point launch for the tiny
+    ones)."""
     rng = np.random.default_rng(13)
     lmax = 4
     sizes = [3, 1, 2, 5, 7, (1 << 20) + 7, 6, 4]
     tabs = np.stack([workloads.radial_table(rng, 9, 2000, 3.0) for _ in sizes])
     radial = sh.Radial(tabs, 3.0)
     srv = Server(4 << 30, n_slots=1)
+    tdt = torch.float64 if dt == "f64" else torch.float32
     atoms, dev_pts, centers = [], [], []
     for k, n in enumerate(sizes):
-        c = rng.uniform(0.0, 10.0, size=3)
-        t = torch.from_numpy(c + rng.uniform(-1.7, 1.7, size=(n, 3))).to(
-            dev, torch.float64 if dt == "f64" else torch.float32).contiguous()
+        c = rng.uniform(0.0, 10.0, size=3).astype(np.float32 if dt == "f32" else np.float64).astype(np.float64)
+        t = torch.from_numpy(c + rng.uniform(-1.7, 1.7, size=(n, 3))).to(dev, tdt).contiguous()
         dev_pts.append(t)
         centers.append(c)
         atoms.append(srv.add_atom(t, c, radial, table=k))
@@ -219,14 +229,61 @@ def test_tiny_requests_in_a_large_group(dev, dt):
         assert srv.wait(t, 60) == DONE
     _say("  batches:", srv.stats()["batches"])
     for k, (t, n) in enumerate(zip(tickets, sizes)):
-        got = srv.result(t, lmax, n, torch.float64 if dt == "f64" else torch.float32).double()
-        toa = torch.tensor([k], dtype=torch.int32, device=dev)
-        ref = sh.sh_projectors(lmax, torch.tensor(centers[k][None], dtype=torch.float64, device=dev),
-                               torch.tensor([0, n], dtype=torch.int64, device=dev),
-                               dev_pts[k].double().contiguous(), radial, table_of_atom=toa)
-        tol = 1e-13 if dt == "f64" else 5e-6
-        assert (got.reshape(-1) - ref).abs().max().item() <= tol, (n, dt)
+        got = srv.result(t, lmax, n, tdt)
+        assert torch.equal(got.reshape(-1), _alone(dev, lmax, centers[k], dev_pts[k], radial, k)), (n, dt)
         srv.release(t)
+    srv.close()
+    radial.close()
+
+
+def test_alone_and_in_a_vector_group_bitwise(dev):
+    """The served-alone-versus-in-the-mix identity where the lane width changes:
+    ten requests of 110,001 to 110,010 points per dtype (lmax 5) are served one at a
+    time (each its own launch, one point per lane), then all at once behind a large
+    request that holds the only stream slot, so that they form one batch whose
+    (dtype, lmax) groups exceed 2^20 points and take the launch with several
+    adjacent points per lane.  Each result is identical bit for bit in both runs
+    and to sh_projectors of its atom alone."""
+    rng = np.random.default_rng(14)
+    lmax = 5
+    sizes = [110_001 + k for k in range(10)]
+    cases = [(n, dt) for dt in ("f64", "f32") for n in sizes]
+    tabs = np.stack([workloads.radial_table(rng, 9, 2000, 3.0) for _ in range(len(cases) + 1)])
+    radial = sh.Radial(tabs, 3.0)
+    srv = Server(24 << 30, n_slots=1)
+    atoms, dev_pts, centers = [], [], []
+    for k, (n, dt) in enumerate(cases):
+        c = rng.uniform(0.0, 10.0, size=3).astype(np.float32 if dt == "f32" else np.float64).astype(np.float64)
+        t = torch.from_numpy(c + rng.uniform(-1.7, 1.7, size=(n, 3))).to(
+            dev, torch.float64 if dt == "f64" else torch.float32).contiguous()
+        dev_pts.append(t)
+        centers.append(c)
+        atoms.append(srv.add_atom(t, c, radial, table=k))
+    nb = 1 << 24  # the blocker: lmax 9, FP64, 12.9 GB of output
+    cb = np.array([5.0, 5.0, 5.0])
+    blk = torch.from_numpy(cb + rng.uniform(-1.7, 1.7, size=(nb, 3))).to(dev).contiguous()
+    ablk = srv.add_atom(blk, cb, radial, table=len(cases))
+    _say("case: served alone vs in a vector-lane group,", len(cases), "requests")
+    alone = []
+    for a, (n, dt) in zip(atoms, cases):
+        t = srv.submit(a, lmax)
+        assert srv.wait(t, 60) == DONE
+        alone.append(srv.result(t, lmax, n, torch.float64 if dt == "f64" else torch.float32).clone())
+        srv.release(t)
+    b0 = srv.stats()["batches"]
+    tb = srv.submit(ablk, 9)
+    tickets = [srv.submit(a, lmax) for a in atoms]
+    for t in [tb] + tickets:
+        assert srv.wait(t, 60) == DONE
+    batches = srv.stats()["batches"] - b0
+    _say("  batches for the blocker and the group:", batches)
+    assert batches == 2  # the blocker alone, then all twenty requests in one batch
+    for k, (t, (n, dt)) in enumerate(zip(tickets, cases)):
+        got = srv.result(t, lmax, n, torch.float64 if dt == "f64" else torch.float32)
+        assert torch.equal(got, alone[k]), (k, dt)
+        assert torch.equal(got.reshape(-1), _alone(dev, lmax, centers[k], dev_pts[k], radial, k)), (k, dt)
+        srv.release(t)
+    srv.release(tb)
     srv.close()
     radial.close()
 
