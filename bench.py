@@ -28,11 +28,14 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fwd_traffic.json")
 
 
 def fwd_source_hash() -> str:
-    """sha256 over the code of the forward kernel's sources, comments and whitespace
-    removed (for matching counter data to the kernel they were taken on)."""
+    """sha256 over the compile flags and the code of the forward kernel's sources,
+    comments and whitespace removed (for matching counter data to the kernel they
+    were taken on)."""
     import hashlib
     import re
+    from paper_2510_05282_amd import build as shbuild
     h = hashlib.sha256()
+    h.update(" ".join(shbuild.compile_flags()).encode())  # the code also depends on how it is compiled
     for f in FWD_SOURCES:
         with open(os.path.join(ROOT, "paper_2510_05282_amd", "csrc", f)) as fh:
             code = re.sub(r"/\*.*?\*/", " ", fh.read(), flags=re.S)
@@ -68,8 +71,8 @@ def _parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="headline only")
     ap.add_argument("--only", default="",
-                    help="comma-separated extra sections to run (sweep, interfaces, projectors, gradient, "
-                         "serving); default: all")
+                    help="comma-separated extra sections to run (sweep, store_probes, interfaces, projectors, "
+                         "gradient, serving); default: all")
     ap.add_argument("--serve-requests", type=int, default=10_000)
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the headline, copy 4 GiB once (calibrates HBM traffic counters)")
@@ -180,6 +183,52 @@ def write_probe(buf, steps):
     total, per = time_launches(lambda: buf.fill_(1.0), steps, 2)
     avg = sum(per) / len(per)
     return {"bytes": buf.numel() * buf.element_size(), "gbs": buf.numel() * buf.element_size() / avg / 1e9}
+
+
+def store_probe_lib():
+    """libshprobe.so (store-pattern probe kernels, built with the library)."""
+    import ctypes
+    path = os.path.join(ROOT, "paper_2510_05282_amd", "libshprobe.so")
+    if not os.path.exists(path):
+        raise SystemExit(f"{path} is not built; run `python -m paper_2510_05282_amd.build`")
+    P = ctypes.CDLL(path)
+    i32, i64, vp = ctypes.c_int, ctypes.c_int64, ctypes.c_void_p
+    P.shp_fill.argtypes = [vp, i64, i32, vp]
+    P.shp_rows.argtypes = [vp, vp, i64, i64, i32, i32, i32, i32, i32, vp]
+    P.shp_fwd_split.argtypes = [vp, vp, i64, i64, i32, i32, i32, vp]
+    return P
+
+
+def bench_store_probes(xyz, out, head, steps):
+    """The headline kernel's store pattern without its arithmetic, and plain fills,
+    over the same buffers: `rows100` loads each lane's two points and writes 100
+    rows of 16 bytes in the headline kernel's launch shape (256 lanes, XCD-ordered
+    tiles, at most 2 workgroups per CU); `rows10` the same with 10 rows; `fill` one
+    16-byte store per lane over the whole output (plain, and with the sc1 cache
+    policy bit).  `frac_of_store_pattern` is the headline kernel's rate over
+    rows100's."""
+    import torch
+    P = store_probe_lib()
+    n = xyz.shape[0]
+    st = torch.cuda.current_stream().cuda_stream
+
+    def chk(rc):
+        if rc != 0:
+            raise RuntimeError(f"store probe rejected its arguments ({rc})")
+
+    res = {}
+    cases = (("rows100", n * (24 + 800), lambda: chk(P.shp_rows(xyz.data_ptr(), out.data_ptr(), n, n, 100, 1, 0, 1, 0, st))),
+             ("rows10", n * (24 + 80), lambda: chk(P.shp_rows(xyz.data_ptr(), out.data_ptr(), n, n, 10, 1, 0, 1, 0, st))),
+             ("fill", n * 800, lambda: chk(P.shp_fill(out.data_ptr(), n * 800, 0, st))),
+             ("fill_sc1", n * 800, lambda: chk(P.shp_fill(out.data_ptr(), n * 800, 4, st))))
+    for name, nbytes, fn in cases:
+        _, per = time_launches(fn, steps, 2)
+        avg = sum(per) / len(per)
+        res[name] = {"ms": avg * 1e3, "bytes": nbytes, "gbs": nbytes / avg / 1e9,
+                     "frac": nbytes / avg / 1e9 / HBM_PEAK_GBS}
+    res["frac_of_store_pattern"] = head["gbs"] / res["rows100"]["gbs"]
+    res["frac_of_fill"] = head["gbs"] / max(res["fill"]["gbs"], res["fill_sc1"]["gbs"])
+    return res
 
 
 def bench_interfaces(sh, xyz, out, steps):
@@ -604,6 +653,11 @@ def main():
         result["write_probe"] = write_probe(out, 5)
         result["roofline"]["frac_of_write_probe"] = head["gbs"] / result["write_probe"]["gbs"]
         del xyz32
+    if want("store_probes") and n % 4096 == 0:  # the probes take whole groups of 8 tiles
+        _log("store-pattern probes")
+        result["store_probes"] = bench_store_probes(xyz, out, head, max(5, args.steps // 2))
+        result["roofline"]["frac_of_store_pattern"] = result["store_probes"]["frac_of_store_pattern"]
+        _log("  ", json.dumps(result["store_probes"]))
     if want("interfaces"):
         _log("interfaces")
         result["interfaces"] = bench_interfaces(sh, xyz, out, max(5, args.steps // 2))
