@@ -263,6 +263,7 @@ typedef struct {
     int64_t points_done;
     uint64_t bytes_in_use, peak_bytes;  /* output bytes admitted (arena) */
     double first_submit_s, last_done_s; /* seconds since creation; -1 before the first submit */
+    double scheduler_cpu_s;             /* CPU time used by the scheduler thread (-1 if unknown) */
 } sh_server_stats_t;
 
 /* A server with an HBM budget of budget_bytes (allocated now), at most

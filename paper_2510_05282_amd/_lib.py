@@ -24,7 +24,8 @@ class ServerStats(ctypes.Structure):
                 ("failed", ctypes.c_int64), ("deferred", ctypes.c_int64),
                 ("batches", ctypes.c_int64), ("points_done", ctypes.c_int64),
                 ("bytes_in_use", ctypes.c_uint64), ("peak_bytes", ctypes.c_uint64),
-                ("first_submit_s", ctypes.c_double), ("last_done_s", ctypes.c_double)]
+                ("first_submit_s", ctypes.c_double), ("last_done_s", ctypes.c_double),
+                ("scheduler_cpu_s", ctypes.c_double)]
 
 
 class ShError(RuntimeError):

@@ -2,6 +2,9 @@
 // executor (host code only; the HIP executor lives in sh_serve.hip).
 #include "sh_server.h"
 
+#include <pthread.h>
+#include <time.h>
+
 #include <algorithm>
 
 #include "../../include/shmi.h"
@@ -72,6 +75,7 @@ Server::Server(std::unique_ptr<Executor> ex, uint64_t budget, int64_t max_pendin
     finished_.resize(ns);
     for (int s = ns - 1; s >= 0; --s) free_slots_.push_back(s);
     st_.first_submit_s = -1.0;
+    notified_ = ex_->set_notify([this] { on_progress(); });
     thr_ = std::thread([this] { loop(); });
 }
 
@@ -84,6 +88,17 @@ Server::~Server()
     }
     cv_work_.notify_all();
     thr_.join();
+    ex_.reset();  // stops the executor's notices while what they touch still exists
+}
+
+// A completion notice from the executor (on one of its threads): wake the scheduler.
+void Server::on_progress()
+{
+    {
+        std::lock_guard<std::mutex> g(mu_);
+        gen_++;
+    }
+    cv_work_.notify_one();
 }
 
 int Server::add_atom(const Atom& a, int* id)
@@ -99,6 +114,8 @@ int Server::add_atom(const Atom& a, int* id)
 
 int Server::submit(int atom, int lmax, int flags, int64_t* ticket)
 {
+    // a request's latency starts before any wait for the lock
+    const Clock::time_point t_submit = Clock::now();
     if (!ticket || lmax < 0 || lmax > SH_LMAX) return SH_EINVAL;
     std::lock_guard<std::mutex> g(mu_);
     if (stop_) return SH_EBUSY;
@@ -114,7 +131,7 @@ int Server::submit(int atom, int lmax, int flags, int64_t* ticket)
     r.flags = flags;
     r.bytes = bytes;
     r.state = kPending;
-    r.t_submit = Clock::now();
+    r.t_submit = t_submit;
     r.refusals_at_submit = refusals_;
     *ticket = int64_t(reqs_.size());
     reqs_.push_back(r);
@@ -291,22 +308,30 @@ void Server::loop()
                 // submit, release or shutdown bumps gen_ while a slot is free (with
                 // every slot busy, new work waits for a completion anyway, so
                 // submitters never contend with this thread for the lock).
-                // busy_ and free_slots_ change only on this thread.
+                // busy_ and free_slots_ change only on this thread.  Short batches
+                // are caught by the polling; when the executor reports completions,
+                // polling stops after kBusySpin and the thread sleeps until a
+                // completion notice (or a submit, release or shutdown) bumps gen_.
                 const uint64_t g = gen_;
                 const bool slot_free = !free_slots_.empty();
                 done_.assign(busy_.size(), 0);
                 early_.resize(busy_.size());
                 for (auto& e : early_) e.clear();
                 lk.unlock();
-                for (bool got = false; !got && !(gen_ != g && (slot_free || stop_));) {
+                const Clock::time_point t_poll = Clock::now();
+                bool got = false;
+                for (;;) {
                     std::this_thread::yield();
                     for (size_t k = 0; k < busy_.size(); ++k) {
                         if (done_[k] == 0) done_[k] = ex_->progress(busy_[k], early_[k]);
                         got = got || done_[k] != 0 || !early_[k].empty();
                     }
+                    if (got || (gen_ != g && (slot_free || stop_))) break;
+                    if (notified_ && Clock::now() - t_poll > kBusySpin) break;
                 }
                 lk.lock();
                 apply_locked();
+                if (!got && notified_) cv_work_.wait(lk, [&] { return stop_ || gen_ != g; });
             } else {
                 // nothing runs and nothing can be admitted: watch for a submit, a
                 // release or shutdown with the lock free for up to kIdleSpin (a
@@ -383,8 +408,14 @@ int Server::drain(double timeout_s)
 
 void Server::stats(Stats* s)
 {
+    clockid_t cid;
+    timespec ts{};
+    double cpu = -1.0;
+    if (pthread_getcpuclockid(thr_.native_handle(), &cid) == 0 && clock_gettime(cid, &ts) == 0)
+        cpu = double(ts.tv_sec) + 1e-9 * double(ts.tv_nsec);
     std::lock_guard<std::mutex> g(mu_);
     *s = st_;
+    s->scheduler_cpu_s = cpu;
 }
 
 int64_t Server::latencies(double* out, int64_t cap)
@@ -407,9 +438,18 @@ namespace {
 class SimExecutor final : public Executor {
 public:
     SimExecutor(int n_slots, double bps, int fail_every, double launch_s)
-        : item_done_(n_slots), next_(n_slots, 0), done_at_(n_slots), fail_(n_slots, false), bps_(bps),
-          fail_every_(fail_every), launch_s_(launch_s)
+        : item_done_(n_slots), next_(n_slots, 0), noticed_(n_slots, 0), done_at_(n_slots), fail_(n_slots, false),
+          bps_(bps), fail_every_(fail_every), launch_s_(launch_s)
     {
+    }
+    ~SimExecutor() override
+    {
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            stop_ = true;
+        }
+        cv_.notify_all();
+        if (waiter_.joinable()) waiter_.join();
     }
     int n_slots() const override { return int(done_at_.size()); }
     int64_t max_items() const override { return 4096; }
@@ -421,50 +461,105 @@ public:
     int launch(int slot, const std::vector<Item>& items) override
     {
         if (launch_s_ > 0) std::this_thread::sleep_for(std::chrono::duration<double>(launch_s_));
-        const Clock::time_point t0 = Clock::now();
-        auto& q = item_done_[slot];
-        q.clear();
         std::vector<int> idx(items.size());
         for (size_t k = 0; k < idx.size(); ++k) idx[k] = int(k);
         std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
             return out_bytes(items[a].atom, items[a].lmax) < out_bytes(items[b].atom, items[b].lmax);
         });
-        double bytes = 0;
-        for (int k : idx) {
-            bytes += double(out_bytes(items[k].atom, items[k].lmax));
-            q.push_back({t0 + std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(bytes / bps_)),
-                         k});
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            const Clock::time_point t0 = Clock::now();
+            auto& q = item_done_[slot];
+            q.clear();
+            double bytes = 0;
+            for (int k : idx) {
+                bytes += double(out_bytes(items[k].atom, items[k].lmax));
+                q.push_back({t0 + std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(bytes / bps_)),
+                             k});
+            }
+            done_at_[slot] =
+                t0 + std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(bytes / bps_));
+            next_[slot] = 0;
+            noticed_[slot] = 0;
+            ++launches_;
+            fail_[slot] = fail_every_ > 0 && launches_ % fail_every_ == 0;
         }
-        done_at_[slot] = t0 + std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(bytes / bps_));
-        next_[slot] = 0;
-        ++launches_;
-        fail_[slot] = fail_every_ > 0 && launches_ % fail_every_ == 0;
+        cv_.notify_all();
         return SH_OK;
     }
     int query(int slot) override
     {
-        if (Clock::now() < done_at_[slot]) return 0;
-        return fail_[slot] ? -1 : 1;
+        std::lock_guard<std::mutex> g(mu_);
+        return query_locked(slot);
     }
     // a failing batch reports nothing early: all its requests fail with it
     int progress(int slot, std::vector<int>& done) override
     {
+        std::lock_guard<std::mutex> g(mu_);
         const Clock::time_point now = Clock::now();
         const auto& q = item_done_[slot];
         while (!fail_[slot] && next_[slot] < q.size() && q[next_[slot]].first <= now)
             done.push_back(q[next_[slot]++].second);
-        return query(slot);
+        return query_locked(slot);
+    }
+    // one thread sleeps until the next item completion of any slot and reports it
+    bool set_notify(std::function<void()> fn) override
+    {
+        if (!fn || waiter_.joinable()) return false;
+        notify_ = std::move(fn);
+        waiter_ = std::thread([this] { watch(); });
+        return true;
     }
 
 private:
+    int query_locked(int slot) const
+    {
+        if (Clock::now() < done_at_[slot]) return 0;
+        return fail_[slot] ? -1 : 1;
+    }
+    void watch()
+    {
+        std::unique_lock<std::mutex> lk(mu_);
+        while (!stop_) {
+            bool any = false;
+            Clock::time_point next{};
+            for (size_t s = 0; s < item_done_.size(); ++s) {
+                if (noticed_[s] >= item_done_[s].size()) continue;
+                const Clock::time_point t = item_done_[s][noticed_[s]].first;
+                if (!any || t < next) next = t;
+                any = true;
+            }
+            if (!any) {
+                cv_.wait(lk);
+                continue;
+            }
+            if (Clock::now() < next) {
+                cv_.wait_until(lk, next);
+                continue;
+            }
+            const Clock::time_point now = Clock::now();
+            for (size_t s = 0; s < item_done_.size(); ++s)
+                while (noticed_[s] < item_done_[s].size() && item_done_[s][noticed_[s]].first <= now) ++noticed_[s];
+            lk.unlock();
+            notify_();
+            lk.lock();
+        }
+    }
+
+    std::mutex mu_;  // everything below; launch/progress on the scheduler thread, watch() on its own
+    std::condition_variable cv_;
     std::vector<std::vector<std::pair<Clock::time_point, int>>> item_done_;  // per slot: (completion, item)
-    std::vector<size_t> next_;  // per slot: first item not yet reported
+    std::vector<size_t> next_;     // per slot: first item not yet reported by progress()
+    std::vector<size_t> noticed_;  // per slot: first item whose completion was not yet notified
     std::vector<Clock::time_point> done_at_;
     std::vector<bool> fail_;
     double bps_;
     int fail_every_;
     double launch_s_;  // host time one launch takes
     int64_t launches_ = 0;
+    bool stop_ = false;
+    std::function<void()> notify_;
+    std::thread waiter_;
 };
 
 }  // namespace

@@ -21,15 +21,31 @@
 #include <atomic>
 #include <condition_variable>
 #include <deque>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
 #include <thread>
 #include <vector>
 
+struct sh_radial;
+
 namespace shs {
 
 using Clock = std::chrono::steady_clock;
+
+// The device table one atom uses: table `table` of a radial handle, in the
+// precision of dtype (SH_F64: double pairs, SH_F32: float pairs).
+struct RadialRef {
+    const void* tab;
+    int lmax;  // channels - 1
+    int n_r;
+    double h, r_max;
+};
+
+// Looks a table up in a radial handle (defined with the handles); SH_EINVAL for a
+// table or dtype out of range.
+int radial_table(sh_radial* radial, int table, int dtype, RadialRef* out);
 
 // A registered atom: its grid points stay on the device for the server's life.
 struct Atom {
@@ -72,6 +88,15 @@ public:
         (void)done;
         return query(slot);
     }
+    // An executor that can tell when work completes calls `fn` (from a thread of
+    // its own) after each completion it would report through progress(), and
+    // returns true here; the scheduler then sleeps instead of polling while long
+    // batches run.  The executor is destroyed before anything `fn` uses.
+    virtual bool set_notify(std::function<void()> fn)
+    {
+        (void)fn;
+        return false;
+    }
 };
 
 // First-fit allocator over [0, capacity) with coalescing, 256-byte granularity.
@@ -108,6 +133,7 @@ struct Stats {
     int64_t points_done;
     uint64_t bytes_in_use, peak_bytes;
     double first_submit_s, last_done_s;  // seconds since server creation
+    double scheduler_cpu_s;              // CPU time the scheduler thread has used
 };
 
 class Server {
@@ -149,9 +175,14 @@ private:
     std::vector<int> free_slots_;
     int busy_slots_ = 0;
     int64_t refusals_ = 0;  // admission attempts refused for lack of budget
-    std::atomic<uint64_t> gen_{0};  // bumped by every submit, release and shutdown
+    std::atomic<uint64_t> gen_{0};  // bumped by every submit, release, shutdown and completion notice
     // how long an idle scheduler watches gen_ before it sleeps on cv_work_
     static constexpr std::chrono::microseconds kIdleSpin{200};
+    // how long the scheduler polls running batches before it sleeps until the
+    // executor reports a completion (when the executor can)
+    static constexpr std::chrono::microseconds kBusySpin{100};
+    bool notified_ = false;  // the executor reports completions (set_notify)
+    void on_progress();
     std::vector<int> busy_, done_;  // scratch of reap(): busy slots and their progress() results
     std::vector<std::vector<int>> early_;    // scratch of reap(): items reported complete per busy slot
     std::vector<std::vector<char>> finished_;  // per slot: which of its requests are already finished
