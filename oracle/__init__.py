@@ -48,6 +48,7 @@ def lib():
         i64, i32, vp = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p
         L.orc_eval_xyz.argtypes = [i32, i64, vp, vp]
         L.orc_eval_xyz_f32.argtypes = [i32, i64, vp, vp]
+        L.orc_eval_xyz_maxerr.argtypes = [i32, i64, vp, vp, i64, vp]
         L.orc_eval_angles.argtypes = [i32, i64, vp, vp, vp]
         L.orc_jacobian_xyz.argtypes = [i32, i64, vp, vp]
         L.orc_grad_xyz.argtypes = [i32, i64, vp, vp, vp]
@@ -87,6 +88,21 @@ def nfun(lmax: int) -> int:
 def row(l: int, m: int) -> int:
     """Flat index of (l, m): l-major, m ascending from -l to l."""
     return l * l + l + m
+
+
+def eval_xyz_maxerr(lmax: int, xyz, got) -> np.ndarray:
+    """Largest |got[row][i] - R_row(xyz_i)| per l over all points, for outputs too
+    large to hold in long double; got is a [F][>= n] float64 array (rows may be
+    longer than n).  Returns float64 [lmax + 1]."""
+    a = np.ascontiguousarray(np.asarray(xyz, dtype=np.float64).reshape(-1, 3))
+    g = np.asarray(got)
+    if g.dtype != np.float64 or g.ndim != 2 or g.shape[0] != nfun(lmax) or g.shape[1] < a.shape[0] \
+            or g.strides[1] != 8:
+        raise ValueError("got must be a float64 [F][>= n] array with contiguous rows")
+    err = np.zeros(lmax + 1)
+    _check(lib().orc_eval_xyz_maxerr(lmax, a.shape[0], _p(a), ctypes.c_void_p(g.ctypes.data),
+                                     ctypes.c_int64(g.strides[0] // 8), _p(err)), "eval_xyz_maxerr")
+    return err
 
 
 def eval_xyz(lmax: int, xyz) -> np.ndarray:

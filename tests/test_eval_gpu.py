@@ -224,6 +224,30 @@ def test_roofline_config_full_size_sampled(dev, orc, lmax):
         assert err.max() <= tol
 
 
+@pytest.mark.timeout(900)
+def test_roofline_config_full_output_fp64(dev, orc):
+    """The headline configuration in full: every value of the lmax 9 FP64 output
+    for the benchmark's 2^26 seeded points (100 rows, 53.7 GB) against the oracle,
+    2^22 points at a time (each chunk copied to the host, the oracle's values formed
+    and compared there without being stored): max abs error <= 1e-13 per l."""
+    n, chunk = 1 << 26, 1 << 22
+    _say("case: full lmax 9 fp64 output, 2^26 points, oracle in chunks of 2^22")
+    pts = workloads.points_roofline(n=n, seed=0)
+    x = torch.from_numpy(pts).to(dev)
+    y = sh.sh_eval(9, x)
+    del x
+    host = torch.empty((100, chunk), dtype=torch.float64).pin_memory()
+    worst = np.zeros(10)
+    for c0 in range(0, n, chunk):
+        host.copy_(y[:, c0:c0 + chunk])
+        worst = np.maximum(worst, orc.eval_xyz_maxerr(9, pts[c0:c0 + chunk], host.numpy()))
+        if c0 % (1 << 24) == 0:
+            _say("  through point", c0 + chunk)
+    _say("  max abs err per l:", ["%.1e" % e for e in worst])
+    del y
+    assert worst.max() <= TOL64
+
+
 def test_multi_launch_chunking(dev, orc):
     """More than 2^28 points: the host splits the batch into several launches;
     check columns on both sides of the split."""

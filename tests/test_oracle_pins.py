@@ -521,3 +521,22 @@ def test_complex_from_angles_mpmath(orc):
                 r = _row(l, m)
                 assert abs(_mpf(re[r, i]) - mp.re(ref)) <= 2e-17
                 assert abs(_mpf(im[r, i]) - mp.im(ref)) <= 2e-17
+
+
+def test_maxerr_helper_matches_stored_values(orc):
+    """The comparison helper for whole outputs (oracle.eval_xyz_maxerr) reports per
+    l the largest deviation of a given array from eval_xyz's values: zero-level for
+    eval_xyz's own values rounded to double (at most half an ulp), the planted
+    error in the l it was planted in, +inf for a NaN, and it honours padded rows."""
+    pts = workloads.points_plain_eval(seed=7, n_random=3000)
+    ref = orc.eval_xyz(9, pts)
+    wide = np.zeros((100, pts.shape[0] + 5))
+    wide[:, :pts.shape[0]] = ref.astype(np.float64)
+    e0 = orc.eval_xyz_maxerr(9, pts, wide)
+    half_ulp = np.abs(ref).astype(np.float64).max(axis=1) * 2.0 ** -53
+    assert np.all(e0 <= np.array([half_ulp[l * l:(l + 1) ** 2].max() for l in range(10)]) * 1.0001)
+    wide[50, 11] += 3e-11  # row 50: l = 7
+    e1 = orc.eval_xyz_maxerr(9, pts, wide)
+    assert abs(e1[7] - 3e-11) < 1e-14 and np.all(np.delete(e1, 7) == np.delete(e0, 7))
+    wide[2, 0] = np.nan  # row 2: l = 1
+    assert np.isinf(orc.eval_xyz_maxerr(9, pts, wide)[1])
