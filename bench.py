@@ -352,8 +352,10 @@ def bench_projectors(sh, workloads, dev, steps):
     radl = sh.Radial(np.stack([workloads.radial_table(rng, 9, 2000, 3.0) for _ in range(na)]), 3.0)
     nl = na * per
     large = {"workload": "64 atoms x 150k points, balls of radius 3", "n_points": nl}
-    for name, lmax, dt in (("lmax6_f64", 6, torch.float64), ("lmax9_f64", 9, torch.float64),
-                           ("lmax6_f32", 6, torch.float32)):
+    for name, lmax, dt in (("lmax0_f64", 0, torch.float64), ("lmax1_f64", 1, torch.float64),
+                           ("lmax3_f64", 3, torch.float64), ("lmax6_f64", 6, torch.float64),
+                           ("lmax9_f64", 9, torch.float64), ("lmax3_f32", 3, torch.float32),
+                           ("lmax6_f32", 6, torch.float32), ("lmax9_f32", 9, torch.float32)):
         F, sz = (lmax + 1) ** 2, (8 if dt == torch.float64 else 4)
         pl, cl = pts.to(dt), cen.to(dt)
         o = torch.empty(F * nl, dtype=dt, device=dev)
@@ -465,14 +467,20 @@ def bench_serving(sh, workloads, dev, n_req):
         atoms = [srv.add_atom(p, r.center, radials[slot[k][0]], table=slot[k][1])
                  for k, (p, r) in enumerate(zip(pts, reqs))]
         torch.cuda.synchronize()
+        cpu0 = srv.stats()["scheduler_cpu_s"]
+        lag = np.empty(n_req)  # how far each submission fell behind its scheduled arrival
         t0 = time.perf_counter()
-        for a, r, ta in zip(atoms, reqs, arrivals):
-            while time.perf_counter() - t0 < ta:
-                pass
+        for k, (a, r, ta) in enumerate(zip(atoms, reqs, arrivals)):
+            now = time.perf_counter() - t0
+            while now < ta:
+                now = time.perf_counter() - t0
+            lag[k] = now - ta
             srv.submit(a, r.lmax, SH_REQ_AUTORELEASE)
         srv.drain(600)
         wall = time.perf_counter() - t0
         st = srv.stats()
+        st["scheduler_cpu_frac"] = (st["scheduler_cpu_s"] - cpu0) / wall
+        st["lag_ms_max"], st["lag_ms_p99"] = float(lag.max() * 1e3), float(np.percentile(lag, 99) * 1e3)
         lat = srv.latencies_ms()
         srv.close()
         return wall, st, lat
@@ -481,7 +489,8 @@ def bench_serving(sh, workloads, dev, n_req):
     rate = n_req / wall
     out["closed_loop"] = {"wall_s": wall, "req_per_s": rate, "points_per_s": total_points / wall,
                           "gbs": total_bytes / wall / 1e9, "batches": st["batches"],
-                          "deferred": st["deferred"], "peak_bytes": st["peak_bytes"]}
+                          "deferred": st["deferred"], "peak_bytes": st["peak_bytes"],
+                          "scheduler_cpu_frac": st["scheduler_cpu_frac"]}
     for key, frac in (("poisson", 0.7), ("poisson_0.3", 0.3)):
         lam = frac * rate
         arr = workloads.request_stream(n_req=n_req, rate=lam, seed=0)
@@ -491,7 +500,9 @@ def bench_serving(sh, workloads, dev, n_req):
                     "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
                     "points_per_s": total_points / span, "gbs": total_bytes / span / 1e9,
                     "batches": st["batches"], "deferred": st["deferred"], "peak_bytes": st["peak_bytes"],
-                    "completed": st["completed"], "failed": st["failed"]}
+                    "completed": st["completed"], "failed": st["failed"],
+                    "scheduler_cpu_frac": st["scheduler_cpu_frac"],
+                    "submit_lag_ms_max": st["lag_ms_max"], "submit_lag_ms_p99": st["lag_ms_p99"]}
     for rad in radials.values():
         rad.close()
     return out
@@ -538,29 +549,80 @@ def _cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(pts, lmax, sample):
-    """The oracle on the host: all its OpenMP threads on `sample` points, then one
-    thread on a 32x smaller sample (comparable with a single-core figure)."""
+def _timed(fn, threads=None):
+    """Seconds one call of fn takes, with `threads` OpenMP threads in the oracle
+    (None: all of them)."""
     import oracle
+    cores = oracle.num_threads()
+    if threads:
+        oracle.set_num_threads(threads)
+    try:
+        t0 = time.perf_counter()
+        fn()
+        return time.perf_counter() - t0
+    finally:
+        oracle.set_num_threads(cores)
+
+
+def cpu_baseline(pts, lmax, sample, sh=None, dev=None):
+    """The oracle on the host.  Headline: all its OpenMP threads on `sample` points
+    of the headline workload, then one thread on a 32x smaller sample (comparable
+    with a single-core figure).  Then the other workloads, all threads and one
+    thread: the plain evaluation of 100,064 points (lmax 9), the 64-atom projector
+    build (lmax 3), the backward pass on 10,000 points (lmax 6).  Last, the FP32
+    error per l of the headline kernel against the oracle at the float inputs, on
+    2^18 points of the headline workload (re-evaluated on the GPU: a point's values
+    do not depend on its batch)."""
+    import numpy as np
+
+    import oracle
+    from paper_2510_05282_amd import workloads
     chunk = 1 << 18
     n = min(sample, pts.shape[0])
     cores = oracle.num_threads()
-    t0 = time.perf_counter()
-    for c in range(0, n, chunk):
-        oracle.eval_xyz(lmax, pts[c:min(n, c + chunk)])
-    dt = time.perf_counter() - t0
+
+    def head(m):
+        for c in range(0, m, chunk):
+            oracle.eval_xyz(lmax, pts[c:min(m, c + chunk)])
+
+    dt = _timed(lambda: head(n))
     n1 = max(1, n // 32)
-    oracle.set_num_threads(1)
-    t1 = time.perf_counter()
-    for c in range(0, n1, chunk):
-        oracle.eval_xyz(lmax, pts[c:min(n1, c + chunk)])
-    dt1 = time.perf_counter() - t1
-    oracle.set_num_threads(cores)
-    return {"value": n / dt, "unit": "points/s", "cores": cores, "kind": "oracle",
-            "sample": f"first {n} points of the same 2^26-point workload, lmax {lmax}, long double, "
-                      f"{dt:.1f} s",
-            "cpu_model": _cpu_model(), "one_thread_value": n1 / dt1,
-            "one_thread_sample": f"first {n1} points, 1 thread, {dt1:.1f} s"}
+    dt1 = _timed(lambda: head(n1), threads=1)
+    res = {"value": n / dt, "unit": "points/s", "cores": cores, "kind": "oracle",
+           "sample": f"first {n} points of the same 2^26-point workload, lmax {lmax}, long double, "
+                     f"{dt:.1f} s",
+           "cpu_model": _cpu_model(), "one_thread_value": n1 / dt1,
+           "one_thread_sample": f"first {n1} points, 1 thread, {dt1:.1f} s"}
+    cfg = {}
+    p1 = workloads.points_plain_eval(seed=0)
+    cfg["plain_eval"] = {"workload": "100,064 points (100,000 isotropic + 64 special), lmax 9, FP64",
+                         "n_points": p1.shape[0]}
+    A = workloads.atom_spheres(seed=0)
+    cfg["projectors"] = {"workload": "64 atoms, r=3 spheres on a 0.2 grid, lmax 3, FP64",
+                         "n_points": int(A.offsets[-1])}
+    pg = workloads.points_gradient(n=10_000, seed=0)
+    G = np.random.default_rng(1).standard_normal((49, pg.shape[0]))
+    cfg["gradient"] = {"workload": "backward pass, 10,000 points, lmax 6, FP64", "n_points": pg.shape[0]}
+    calls = {"plain_eval": lambda: oracle.eval_xyz(9, p1),
+             "projectors": lambda: oracle.projectors(3, A.centers, A.offsets, A.points, A.tables, A.r_max),
+             "gradient": lambda: oracle.grad_xyz(6, pg, G)}
+    for key, fn in calls.items():
+        ta, t1 = _timed(fn), _timed(fn, threads=1)
+        cfg[key].update({"points_per_s": cfg[key]["n_points"] / ta, "one_thread_points_per_s": cfg[key]["n_points"] / t1,
+                         "seconds": ta, "one_thread_seconds": t1})
+    res["configs"] = cfg
+    if sh is not None:
+        import torch
+        idx = np.sort(np.random.default_rng(11).choice(pts.shape[0], 1 << 18, replace=False))
+        p32 = np.ascontiguousarray(pts[idx].astype(np.float32))
+        got = sh.sh_eval_f32(lmax, torch.from_numpy(p32).to(dev)).cpu().numpy()
+        ref = oracle.eval_xyz(lmax, p32)
+        err = np.abs(got.astype(np.longdouble) - ref).max(axis=1).astype(np.float64)
+        res["fp32_error_per_l"] = {"max_abs_err": [float(err[l * l:(l + 1) ** 2].max()) for l in range(lmax + 1)],
+                                   "bound": 5e-6,
+                                   "sample": "2^18 random points of the headline workload rounded to float; "
+                                             "oracle at the float inputs"}
+    return res
 
 
 def main():
@@ -649,6 +711,15 @@ def main():
             _log("  ", json.dumps({k: sweep[k] for k in (f"f64_l{lmax}", f"f32_l{lmax}")}))
         result["fp32"] = sweep["f32_l9"]
         result["lmax_sweep"] = sweep
+        # the plain-evaluation workload: 100,064 points (a parity configuration, far too
+        # small to fill the GPU: launch-bound)
+        p1 = torch.from_numpy(workloads.points_plain_eval(seed=0)).to(dev)
+        o1 = torch.empty((100, p1.shape[0]), dtype=torch.float64, device=dev)
+        _, per = time_launches(lambda: sh.sh_eval(9, p1, out=o1), 20, 3)
+        t1 = sum(per) / len(per)
+        result["plain_eval"] = {"workload": "100,064 points, lmax 9, FP64", "n_points": p1.shape[0],
+                                "kernel_ms": t1 * 1e3, "points_per_s": p1.shape[0] / t1}
+        del p1, o1
         _log("write probe")
         result["write_probe"] = write_probe(out, 5)
         result["roofline"]["frac_of_write_probe"] = head["gbs"] / result["write_probe"]["gbs"]
@@ -682,7 +753,16 @@ def main():
 
     if not args.no_cpu_baseline:
         _log("cpu baseline")
-        result["cpu_baseline"] = cpu_baseline(pts, 9, args.cpu_sample)
+        cb = cpu_baseline(pts, 9, args.cpu_sample, sh, dev)
+        # the GPU's rate on the same workloads, where this run measured it
+        gpu = {"plain_eval": result.get("plain_eval", {}).get("points_per_s"),
+               "projectors": result.get("projectors", {}).get("points_per_s"),
+               "gradient": result.get("gradient", {}).get("backward_points_per_s")}
+        for k, v in gpu.items():
+            cb["configs"][k]["gpu_points_per_s"] = v
+        if "fp32_error_per_l" in cb:
+            result.setdefault("fp32", {})["max_abs_err_per_l"] = cb.pop("fp32_error_per_l")
+        result["cpu_baseline"] = cb
     result["paper_context"] = paper_context(result)
     print(json.dumps(result), flush=True)
 

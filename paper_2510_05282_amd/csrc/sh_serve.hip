@@ -17,12 +17,6 @@
 #include <string.h>
 
 #include <algorithm>
-#include <atomic>
-#include <condition_variable>
-#include <functional>
-#include <memory>
-#include <mutex>
-#include <thread>
 #include <utility>
 
 #include "../../include/shmi.h"
@@ -135,12 +129,9 @@ public:
         }
         for (Slot& s : slots_) {
             s.group_done.assign(kMaxGroups, nullptr);
-            s.w.reset(new Waiter());
             bool events_ok = true;
-            // blocking-sync events: a thread waiting on one sleeps instead of spinning
             for (hipEvent_t& ev : s.group_done)
-                events_ok = events_ok &&
-                            hipEventCreateWithFlags(&ev, hipEventDisableTiming | hipEventBlockingSync) == hipSuccess;
+                events_ok = events_ok && hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess;
             if (!events_ok || hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||
                 hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess ||
                 hipHostMalloc(reinterpret_cast<void**>(&s.host), kSlotBytes) != hipSuccess ||
@@ -157,17 +148,8 @@ public:
     }
     ~HipExecutor() override
     {
-        for (Slot& s : slots_)
+        for (Slot& s : slots_) {
             if (s.stream) (void)hipStreamSynchronize(s.stream);
-        // every recorded event has completed: the waiters return from their waits
-        wstop_ = true;
-        for (Slot& s : slots_) {
-            if (!s.w) continue;
-            { std::lock_guard<std::mutex> g(s.w->mu); }
-            s.w->cv.notify_all();
-        }
-        for (std::thread& t : waiters_) t.join();
-        for (Slot& s : slots_) {
             if (s.dev) (void)hipFree(s.dev);
             if (s.host) (void)hipHostFree(s.host);
             if (s.done) (void)hipEventDestroy(s.done);
@@ -265,14 +247,6 @@ public:
             s.group_end.push_back(int(s.group_items.size()));
         }
         if (e == hipSuccess) e = hipEventRecord(s.done, s.stream);
-        if (e == hipSuccess && !waiters_.empty()) {
-            {
-                std::lock_guard<std::mutex> g(s.w->mu);
-                s.w->n_events = int(launch_order_.size());
-                s.w->armed++;
-            }
-            s.w->cv.notify_one();
-        }
         if (e != hipSuccess) {
             // groups launched before the failure may still be writing into outputs the
             // scheduler is about to release: let them finish first
@@ -305,44 +279,7 @@ public:
         return query(slot);
     }
 
-    // one thread per slot waits (blocking, no spinning) on the group events of the
-    // slot's batch in launch order and calls fn after each
-    bool set_notify(std::function<void()> fn) override
-    {
-        if (!fn || !waiters_.empty() || slots_.empty()) return false;
-        notify_ = std::move(fn);
-        for (size_t k = 0; k < slots_.size(); ++k) waiters_.emplace_back([this, k] { watch(slots_[k]); });
-        return true;
-    }
-
 private:
-    struct Waiter {
-        std::mutex mu;
-        std::condition_variable cv;
-        uint64_t armed = 0;  // batches launched on the slot
-        int n_events = 0;    // group events of the latest batch
-    };
-    struct Slot;
-    void watch(Slot& s)
-    {
-        uint64_t seen = 0;
-        std::unique_lock<std::mutex> lk(s.w->mu);
-        for (;;) {
-            s.w->cv.wait(lk, [&] { return wstop_.load() || s.w->armed != seen; });
-            if (s.w->armed == seen) return;  // stopping, nothing new to watch
-            seen = s.w->armed;
-            const int n = s.w->n_events;
-            lk.unlock();
-            // a batch launched on the slot after this one re-records these events;
-            // waiting on a newer recording only delays a notice
-            for (int q = 0; q < n; ++q) {
-                (void)hipEventSynchronize(s.group_done[q]);
-                notify_();
-            }
-            lk.lock();
-        }
-    }
-
     static constexpr int64_t kMaxItems = 8192;
     // per slot: up to kMaxItems descriptors followed by as many first-tile indices
     static constexpr size_t kSlotBytes = (sizeof(shk::ServeDesc) + sizeof(int64_t)) * kMaxItems;
@@ -357,11 +294,7 @@ private:
         int next = 0;                        // first group not yet reported complete
         shk::ServeDesc* host = nullptr;
         shk::ServeDesc* dev = nullptr;
-        std::unique_ptr<Waiter> w;           // the slot's completion watcher
     };
-    std::function<void()> notify_;
-    std::vector<std::thread> waiters_;
-    std::atomic<bool> wstop_{false};
     std::vector<Slot> slots_;
     void* arena_ = nullptr;
     std::vector<int> order_;                      // launch() scratch: items sorted by group

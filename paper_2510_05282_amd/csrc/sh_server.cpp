@@ -3,6 +3,7 @@
 #include "sh_server.h"
 
 #include <pthread.h>
+#include <sys/prctl.h>
 #include <time.h>
 
 #include <algorithm>
@@ -75,7 +76,6 @@ Server::Server(std::unique_ptr<Executor> ex, uint64_t budget, int64_t max_pendin
     finished_.resize(ns);
     for (int s = ns - 1; s >= 0; --s) free_slots_.push_back(s);
     st_.first_submit_s = -1.0;
-    notified_ = ex_->set_notify([this] { on_progress(); });
     thr_ = std::thread([this] { loop(); });
 }
 
@@ -88,17 +88,6 @@ Server::~Server()
     }
     cv_work_.notify_all();
     thr_.join();
-    ex_.reset();  // stops the executor's notices while what they touch still exists
-}
-
-// A completion notice from the executor (on one of its threads): wake the scheduler.
-void Server::on_progress()
-{
-    {
-        std::lock_guard<std::mutex> g(mu_);
-        gen_++;
-    }
-    cv_work_.notify_one();
 }
 
 int Server::add_atom(const Atom& a, int* id)
@@ -248,6 +237,8 @@ bool Server::reap(std::unique_lock<std::mutex>& lk)
 
 void Server::loop()
 {
+    // naps of a few microseconds need a small timer slack (the default adds ~50 us)
+    (void)prctl(PR_SET_TIMERSLACK, 1000UL, 0UL, 0UL, 0UL);
     std::unique_lock<std::mutex> lk(mu_);
     for (;;) {
         bool prog = reap(lk);
@@ -309,9 +300,10 @@ void Server::loop()
                 // every slot busy, new work waits for a completion anyway, so
                 // submitters never contend with this thread for the lock).
                 // busy_ and free_slots_ change only on this thread.  Short batches
-                // are caught by the polling; when the executor reports completions,
-                // polling stops after kBusySpin and the thread sleeps until a
-                // completion notice (or a submit, release or shutdown) bumps gen_.
+                // are caught by back-to-back polls; after kBusySpin the thread naps
+                // between polls (kNapMin doubling to kNapMax), which bounds the CPU
+                // it takes while long batches run and delays noticing their end by
+                // at most one nap.
                 const uint64_t g = gen_;
                 const bool slot_free = !free_slots_.empty();
                 done_.assign(busy_.size(), 0);
@@ -319,19 +311,21 @@ void Server::loop()
                 for (auto& e : early_) e.clear();
                 lk.unlock();
                 const Clock::time_point t_poll = Clock::now();
-                bool got = false;
-                for (;;) {
-                    std::this_thread::yield();
+                std::chrono::microseconds nap = kNapMin;
+                for (bool got = false; !got && !(gen_ != g && (slot_free || stop_));) {
+                    if (Clock::now() - t_poll < kBusySpin) {
+                        std::this_thread::yield();
+                    } else {
+                        std::this_thread::sleep_for(nap);
+                        nap = std::min(nap * 2, kNapMax);
+                    }
                     for (size_t k = 0; k < busy_.size(); ++k) {
                         if (done_[k] == 0) done_[k] = ex_->progress(busy_[k], early_[k]);
                         got = got || done_[k] != 0 || !early_[k].empty();
                     }
-                    if (got || (gen_ != g && (slot_free || stop_))) break;
-                    if (notified_ && Clock::now() - t_poll > kBusySpin) break;
                 }
                 lk.lock();
                 apply_locked();
-                if (!got && notified_) cv_work_.wait(lk, [&] { return stop_ || gen_ != g; });
             } else {
                 // nothing runs and nothing can be admitted: watch for a submit, a
                 // release or shutdown with the lock free for up to kIdleSpin (a
@@ -438,18 +432,9 @@ namespace {
 class SimExecutor final : public Executor {
 public:
     SimExecutor(int n_slots, double bps, int fail_every, double launch_s)
-        : item_done_(n_slots), next_(n_slots, 0), noticed_(n_slots, 0), done_at_(n_slots), fail_(n_slots, false),
-          bps_(bps), fail_every_(fail_every), launch_s_(launch_s)
+        : item_done_(n_slots), next_(n_slots, 0), done_at_(n_slots), fail_(n_slots, false), bps_(bps),
+          fail_every_(fail_every), launch_s_(launch_s)
     {
-    }
-    ~SimExecutor() override
-    {
-        {
-            std::lock_guard<std::mutex> g(mu_);
-            stop_ = true;
-        }
-        cv_.notify_all();
-        if (waiter_.joinable()) waiter_.join();
     }
     int n_slots() const override { return int(done_at_.size()); }
     int64_t max_items() const override { return 4096; }
@@ -480,11 +465,9 @@ public:
             done_at_[slot] =
                 t0 + std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(bytes / bps_));
             next_[slot] = 0;
-            noticed_[slot] = 0;
             ++launches_;
             fail_[slot] = fail_every_ > 0 && launches_ % fail_every_ == 0;
         }
-        cv_.notify_all();
         return SH_OK;
     }
     int query(int slot) override
@@ -502,64 +485,21 @@ public:
             done.push_back(q[next_[slot]++].second);
         return query_locked(slot);
     }
-    // one thread sleeps until the next item completion of any slot and reports it
-    bool set_notify(std::function<void()> fn) override
-    {
-        if (!fn || waiter_.joinable()) return false;
-        notify_ = std::move(fn);
-        waiter_ = std::thread([this] { watch(); });
-        return true;
-    }
-
 private:
     int query_locked(int slot) const
     {
         if (Clock::now() < done_at_[slot]) return 0;
         return fail_[slot] ? -1 : 1;
     }
-    void watch()
-    {
-        std::unique_lock<std::mutex> lk(mu_);
-        while (!stop_) {
-            bool any = false;
-            Clock::time_point next{};
-            for (size_t s = 0; s < item_done_.size(); ++s) {
-                if (noticed_[s] >= item_done_[s].size()) continue;
-                const Clock::time_point t = item_done_[s][noticed_[s]].first;
-                if (!any || t < next) next = t;
-                any = true;
-            }
-            if (!any) {
-                cv_.wait(lk);
-                continue;
-            }
-            if (Clock::now() < next) {
-                cv_.wait_until(lk, next);
-                continue;
-            }
-            const Clock::time_point now = Clock::now();
-            for (size_t s = 0; s < item_done_.size(); ++s)
-                while (noticed_[s] < item_done_[s].size() && item_done_[s][noticed_[s]].first <= now) ++noticed_[s];
-            lk.unlock();
-            notify_();
-            lk.lock();
-        }
-    }
-
-    std::mutex mu_;  // everything below; launch/progress on the scheduler thread, watch() on its own
-    std::condition_variable cv_;
+    std::mutex mu_;  // guards everything below (launch, query and progress may come from any thread)
     std::vector<std::vector<std::pair<Clock::time_point, int>>> item_done_;  // per slot: (completion, item)
-    std::vector<size_t> next_;     // per slot: first item not yet reported by progress()
-    std::vector<size_t> noticed_;  // per slot: first item whose completion was not yet notified
+    std::vector<size_t> next_;  // per slot: first item not yet reported by progress()
     std::vector<Clock::time_point> done_at_;
     std::vector<bool> fail_;
     double bps_;
     int fail_every_;
     double launch_s_;  // host time one launch takes
     int64_t launches_ = 0;
-    bool stop_ = false;
-    std::function<void()> notify_;
-    std::thread waiter_;
 };
 
 }  // namespace

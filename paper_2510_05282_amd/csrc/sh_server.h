@@ -21,7 +21,6 @@
 #include <atomic>
 #include <condition_variable>
 #include <deque>
-#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -87,15 +86,6 @@ public:
     {
         (void)done;
         return query(slot);
-    }
-    // An executor that can tell when work completes calls `fn` (from a thread of
-    // its own) after each completion it would report through progress(), and
-    // returns true here; the scheduler then sleeps instead of polling while long
-    // batches run.  The executor is destroyed before anything `fn` uses.
-    virtual bool set_notify(std::function<void()> fn)
-    {
-        (void)fn;
-        return false;
     }
 };
 
@@ -175,14 +165,14 @@ private:
     std::vector<int> free_slots_;
     int busy_slots_ = 0;
     int64_t refusals_ = 0;  // admission attempts refused for lack of budget
-    std::atomic<uint64_t> gen_{0};  // bumped by every submit, release, shutdown and completion notice
+    std::atomic<uint64_t> gen_{0};  // bumped by every submit, release and shutdown
     // how long an idle scheduler watches gen_ before it sleeps on cv_work_
     static constexpr std::chrono::microseconds kIdleSpin{200};
-    // how long the scheduler polls running batches before it sleeps until the
-    // executor reports a completion (when the executor can)
-    static constexpr std::chrono::microseconds kBusySpin{100};
-    bool notified_ = false;  // the executor reports completions (set_notify)
-    void on_progress();
+    // while batches run: poll their completion back to back for kBusySpin, then
+    // with naps between polls that double from kNapMin up to kNapMax
+    static constexpr std::chrono::microseconds kBusySpin{200};
+    static constexpr std::chrono::microseconds kNapMin{20};
+    static constexpr std::chrono::microseconds kNapMax{200};
     std::vector<int> busy_, done_;  // scratch of reap(): busy slots and their progress() results
     std::vector<std::vector<int>> early_;    // scratch of reap(): items reported complete per busy slot
     std::vector<std::vector<char>> finished_;  // per slot: which of its requests are already finished
