@@ -76,6 +76,10 @@ def _parse():
     ap.add_argument("--serve-requests", type=int, default=10_000)
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the headline, copy 4 GiB once (calibrates HBM traffic counters)")
+    ap.add_argument("--store-sweep", action="store_true",
+                    help="no benchmark: time the store-pattern probe variants (rows split over XCDs, tile "
+                         "orders, cache-policy bits, the forward kernel with split rows) on the headline "
+                         "workload and print one JSON line per variant")
     ap.add_argument("--traffic-from", nargs="+", metavar="CSV",
                     help="no GPU work: turn the counter_collection.csv files of a --pmc FETCH_SIZE and a "
                          "--pmc WRITE_SIZE run of `--copy-probe` (and optionally a --pmc "
@@ -229,6 +233,46 @@ def bench_store_probes(xyz, out, head, steps):
     res["frac_of_store_pattern"] = head["gbs"] / res["rows100"]["gbs"]
     res["frac_of_fill"] = head["gbs"] / max(res["fill"]["gbs"], res["fill_sc1"]["gbs"])
     return res
+
+
+def store_sweep(sh, xyz, out, steps):
+    """Variants of the headline kernel's store pattern (libshprobe.so), each timed
+    like the headline: the 100-row pattern with its rows split over 1, 2, 4 or 8
+    workgroups per tile (order 0: each split on its own XCDs, XCD-contiguous tiles;
+    order 1: hardware order, every XCD on the same tiles), with 16 to 128 tile
+    ranges (orders 2-5), with each cache-policy variant of the store (modes 1-8),
+    and the lmax 9 FP64 forward kernel itself with the same splits and orders."""
+    P = store_probe_lib()
+    import torch
+    n = xyz.shape[0]
+    st = torch.cuda.current_stream().cuda_stream
+    B = n * 824
+
+    def one(name, fn, nbytes=B):
+        _, per = time_launches(fn, steps, 2)
+        avg = sum(per) / len(per)
+        print(json.dumps({"case": name, "ms": avg * 1e3, "gbs": nbytes / avg / 1e9,
+                          "frac": nbytes / avg / 1e9 / HBM_PEAK_GBS}), flush=True)
+
+    def chk(rc):
+        if rc != 0:
+            raise RuntimeError(f"store probe rejected its arguments ({rc})")
+
+    x, o = xyz.data_ptr(), out.data_ptr()
+    one("sh_eval lmax 9 fp64", lambda: sh.sh_eval(9, xyz, out=out.view(-1)[: 100 * n].view(100, n)))
+    for split in (1, 2, 4, 8):
+        for order in (0, 1):
+            for cap in (0, 1):
+                one(f"rows100 split {split} order {order} cap {cap}",
+                    lambda: chk(P.shp_rows(x, o, n, n, 100, split, order, cap, 0, st)))
+                one(f"fwd lmax 9 split {split} order {order} cap {cap}",
+                    lambda: chk(P.shp_fwd_split(x, o, n, n, split, order, cap, st)))
+    for order in (2, 3, 4, 5):
+        one(f"rows100 ranges {8 << (order - 1)} cap 1", lambda: chk(P.shp_rows(x, o, n, n, 100, 1, order, 1, 0, st)))
+        one(f"fwd lmax 9 ranges {8 << (order - 1)} cap 1", lambda: chk(P.shp_fwd_split(x, o, n, n, 1, order, 1, st)))
+    for mode in range(1, 9):
+        one(f"rows100 store mode {mode}", lambda: chk(P.shp_rows(x, o, n, n, 100, 1, 0, 1, mode, st)))
+        one(f"fill store mode {mode}", lambda: chk(P.shp_fill(o, n * 800, mode, st)), n * 800)
 
 
 def bench_interfaces(sh, xyz, out, steps):
@@ -660,6 +704,11 @@ def main():
     xyz = torch.from_numpy(pts).to(dev)
     out = torch.empty((100, n), dtype=torch.float64, device=dev)
 
+    if args.store_sweep:
+        if n % 4096:
+            raise SystemExit("--store-sweep needs --n a multiple of 4096")
+        store_sweep(sh, xyz, out, max(5, args.steps // 2))
+        return
     _log("headline: lmax 9 fp64")
     head = bench_forward(sh, xyz, out, 9, args.steps, args.warmup)
     _log("  ", json.dumps(head))

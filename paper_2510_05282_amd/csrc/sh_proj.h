@@ -123,14 +123,58 @@ __device__ __forceinline__ void proj_point(double px, double py, double pz, cons
                          [&](int f, TIO v) { out[int64_t(f) * stride] = R[l_of_row(f)] * v; });
 }
 
+// Stores the PPL values of vector o (adjacent points) to dst[0 .. PPL-1] with the
+// widest stores the alignment allows: H leading elements one by one up to a
+// 16-byte boundary, 16-byte vectors, then the rest one by one (H is a
+// compile-time case of the run's alignment).
+template <typename TIO, int PPL, int H, typename V>
+__device__ __forceinline__ void store_run_from(TIO* __restrict__ dst, V o)
+{
+    constexpr int UNIT = 16 / int(sizeof(TIO));
+    constexpr int NVEC = H < PPL ? (PPL - H) / UNIT : 0;
+    static_for<0, (H < PPL ? H : PPL)>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        dst[q] = lane<V, PPL>(o, q);
+    });
+    static_for<0, NVEC>([&](auto kc) {
+        constexpr int i0 = H + decltype(kc)::value * UNIT;
+        typename vec_of<TIO, UNIT>::type w;
+        static_for<0, UNIT>([&](auto uc) {
+            constexpr int u = decltype(uc)::value;
+            w[u] = lane<V, PPL>(o, i0 + u);
+        });
+        *reinterpret_cast<typename vec_of<TIO, UNIT>::type*>(dst + i0) = w;
+    });
+    static_for<(H < PPL ? H : PPL) + NVEC * UNIT, PPL>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        dst[q] = lane<V, PPL>(o, q);
+    });
+}
+
+// The first nvalid of the PPL values of o to dst (element-aligned).
+template <typename TIO, int PPL, typename V>
+__device__ __forceinline__ void store_run(TIO* __restrict__ dst, V o, int nvalid)
+{
+    constexpr int UNIT = 16 / int(sizeof(TIO));
+    if (nvalid < PPL || PPL < UNIT) {
+#pragma unroll
+        for (int q = 0; q < PPL; ++q)
+            if (q < nvalid) dst[q] = lane<V, PPL>(o, q);
+        return;
+    }
+    const int a = int((reinterpret_cast<uintptr_t>(dst) / sizeof(TIO)) & (UNIT - 1));
+    const int head = (UNIT - a) & (UNIT - 1);
+    static_for<0, UNIT>([&](auto hc) {
+        if (head == decltype(hc)::value) store_run_from<TIO, PPL, decltype(hc)::value>(dst, o);
+    });
+}
+
 // The same for PPL adjacent points of one table and centre, evaluated together
 // (the polynomials on PPL-wide vectors, which keeps more independent work in each
 // lane): point q's coordinates are (px[q], py[q], pz[q]) and row f of point q goes
 // to out[f * stride + q], for the first nvalid points only (the others are computed
-// and dropped, so a tail lane runs the same code).  A row whose address is aligned
-// for a PPL-wide vector is written with one vector store, any other element by
-// element; the alignment of row f depends only on f mod PPL, so it is worked out
-// once per lane.
+// and dropped, so a tail lane runs the same code).  Each row's run of PPL values is
+// written with 16-byte stores where its alignment allows (store_run).
 template <int LMAX, typename TIO, int PPL>
 __device__ __forceinline__ void proj_points(const double (&px)[PPL], const double (&py)[PPL], const double (&pz)[PPL],
                                             const double c[3], const knot_t<TIO>* __restrict__ tab, int ch,
@@ -151,36 +195,35 @@ __device__ __forceinline__ void proj_points(const double (&px)[PPL], const doubl
         lane<V, PPL>(z, q) = TIO(zb);
         lane<V, PPL>(k, q) = TIO(keep);
     }
-    const int m0 = int((reinterpret_cast<uintptr_t>(out) / sizeof(TIO)) & (PPL - 1));  // out is TIO-aligned
-    const int ms = int(stride & (PPL - 1));
-    bool aligned[PPL];
-#pragma unroll
-    for (int q = 0; q < PPL; ++q) aligned[q] = nvalid == PPL && ((m0 + q * ms) & (PPL - 1)) == 0;
     eval_unit<LMAX, V>(x, y, z, k, [&](int f, V v) {
         const int l = l_of_row(f);
         V r;
 #pragma unroll
         for (int q = 0; q < PPL; ++q) lane<V, PPL>(r, q) = R[q][l];
-        V o = r * v;
-        TIO* dst = out + int64_t(f) * stride;
-        if (aligned[f & (PPL - 1)]) {
-            *reinterpret_cast<V*>(dst) = o;
-        } else {
-#pragma unroll
-            for (int q = 0; q < PPL; ++q)
-                if (q < nvalid) dst[q] = lane<V, PPL>(o, q);
-        }
+        store_run<TIO, PPL>(out + int64_t(f) * stride, r * v, nvalid);
     });
 }
 
 // Lane width of the projector and serving launches.  Several adjacent points per
-// lane (two FP64 or four FP32: 16-byte row stores) raise the throughput of a launch
-// that fills the GPU many times over (measured on 64 x 150k-point builds: +35% at
-// lmax 6 in FP64, +10-21% at lmax 3-9 in FP32), but lengthen each workgroup, which
-// is what a launch too small to fill the GPU waits for; launches below
+// lane (two FP64 at lmax >= 4, four FP64 below, four FP32: row stores of 16 bytes
+// or more) raise the throughput of a launch that fills the GPU many times over
+// (measured on 64 x 150k-point builds: +35% at lmax 6 in FP64, +10-21% at lmax 3-9
+// in FP32; four FP64 points instead of two: +5-17% at lmax 0-3 with the LDS cap
+// below, -7% at lmax 6; eight: slower everywhere), but lengthen each workgroup,
+// which is what a launch too small to fill the GPU waits for; launches below
 // kProjVecPoints points keep one point per lane.
-template <typename TIO> constexpr int kProjPpl = sizeof(TIO) == 8 ? 2 : 4;
+template <typename TIO, int LMAX> constexpr int kProjPpl = sizeof(TIO) == 8 ? (LMAX <= 3 ? 4 : 2) : 4;
 constexpr int64_t kProjVecPoints = int64_t(1) << 20;
+
+// LDS reserved (not used) by the launches with several points per lane: at most 2
+// resident workgroups per CU, which keeps each row's concurrent writes in a
+// smaller window (as for the forward kernel).  Measured on 64 x 150k-point builds:
+// FP64 +1-13% (lmax 0-9, with 4 points per lane at lmax <= 3), FP32 +5-12% at
+// lmax >= 2, -1-2% at lmax 0-1 (no cap there).
+template <typename TIO, int LMAX> constexpr size_t kProjCapLds = (sizeof(TIO) == 4 && LMAX <= 1) ? 0 : 54 * 1024;
+
+// Lane width of a launch of n points.
+template <typename TIO, int LMAX> constexpr int proj_ppl(int64_t n) { return n >= kProjVecPoints ? kProjPpl<TIO, LMAX> : 1; }
 
 // Wave-wide search over n sorted keys: the last k in [0, n) with keys[k] <= x,
 // or -1 if there is none.  Every lane must be active and pass the same x; each

@@ -16,7 +16,8 @@
 // workgroups remapped so each XCD works through one contiguous range of atoms
 // (their tables then stay in that XCD's L2); the atom of a wave found by one
 // wave-wide search; plain stores; one point per lane, or, for builds of at least
-// kProjVecPoints points, kProjPpl adjacent points per lane evaluated together.
+// kProjVecPoints points, kProjPpl adjacent points per lane evaluated together, with
+// at most 2 resident workgroups per CU (kProjCapLds).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -162,6 +163,7 @@ template <int LMAX, typename TIO, int P>
 static hipError_t launch_proj_p(const ProjArgs<TIO>& A, hipStream_t s)
 {
     const SplineGrid g{A.n_r, A.h, 1.0 / A.h, A.r_max, A.h * A.h / 6.0};
+    const size_t lds = P > 1 ? kProjCapLds<TIO, LMAX> : 0;
     for (int64_t j0 = 0; j0 < A.n_points; j0 += kProjChunk) {
         const int64_t nc = A.n_points - j0 < kProjChunk ? A.n_points - j0 : kProjChunk;
         const dim3 grid = dim3(unsigned((nc + 256 * P - 1) / (256 * P))), block = dim3(256);
@@ -170,7 +172,7 @@ static hipError_t launch_proj_p(const ProjArgs<TIO>& A, hipStream_t s)
                                A.n_atoms, A.points, A.n_points, A.table, A.tab_ch, A.n_tables, A.table_of_atom, g,
                                A.out, j0);
         else
-            hipLaunchKernelGGL((proj_kernel<LMAX, TIO, P, false>), grid, block, 0, s, A.centers, A.offsets,
+            hipLaunchKernelGGL((proj_kernel<LMAX, TIO, P, false>), grid, block, lds, s, A.centers, A.offsets,
                                A.n_atoms, A.points, A.n_points, A.table, A.tab_ch, A.n_tables, A.table_of_atom, g,
                                A.out, j0);
         const hipError_t e = hipGetLastError();
@@ -182,7 +184,7 @@ static hipError_t launch_proj_p(const ProjArgs<TIO>& A, hipStream_t s)
 template <int LMAX, typename TIO>
 static hipError_t launch_proj_l(const ProjArgs<TIO>& A, hipStream_t s)
 {
-    return A.n_points >= kProjVecPoints ? launch_proj_p<LMAX, TIO, kProjPpl<TIO>>(A, s)
+    return A.n_points >= kProjVecPoints ? launch_proj_p<LMAX, TIO, kProjPpl<TIO, LMAX>>(A, s)
                                         : launch_proj_p<LMAX, TIO, 1>(A, s);
 }
 

@@ -86,10 +86,19 @@ static void launch_group_l(int ppl, int64_t tiles, const ServeDesc* descs, const
     if (ppl == 1)
         hipLaunchKernelGGL((serve_kernel<LMAX, TIO, 1>), grid, block, 0, s, descs, tile0, n);
     else
-        hipLaunchKernelGGL((serve_kernel<LMAX, TIO, kProjPpl<TIO>>), grid, block, 0, s, descs, tile0, n);
+        hipLaunchKernelGGL((serve_kernel<LMAX, TIO, kProjPpl<TIO, LMAX>>), grid, block, (kProjCapLds<TIO, LMAX>), s,
+                           descs, tile0, n);
 }
 
-// ppl is 1 or kProjPpl<TIO>
+// Lane width of a group of n points of one (dtype, lmax): 1 or kProjPpl.
+static int group_ppl(int dtype, int lmax, int64_t n)
+{
+    if (n < kProjVecPoints) return 1;
+    if (dtype == SH_F32) return kProjPpl<float, 9>;  // the same for every lmax
+    return lmax <= 3 ? kProjPpl<double, 3> : kProjPpl<double, 9>;
+}
+
+// ppl is 1 or kProjPpl<TIO, lmax>
 template <typename TIO>
 static hipError_t launch_group(int lmax, int ppl, int64_t tiles, const ServeDesc* descs, const int64_t* tile0, int n,
                                hipStream_t s)
@@ -188,7 +197,7 @@ public:
         for (Group& g : groups_) {
             const Item& it = items[order_[g.first]];
             const bool f64 = it.atom.dtype == SH_F64;
-            g.ppl = g.tiles >= shk::kProjVecPoints ? (f64 ? shk::kProjPpl<double> : shk::kProjPpl<float>) : 1;
+            g.ppl = shk::group_ppl(it.atom.dtype, it.lmax, g.tiles);
             g.bytes = g.tiles * (it.lmax + 1) * (it.lmax + 1) * (f64 ? 8 : 4);  // output bytes
             g.tiles = 0;
         }
@@ -309,9 +318,9 @@ private:
                                       hipMemcpyHostToDevice, s.stream);
         const int64_t* tile0 = reinterpret_cast<const int64_t*>(s.dev + 1);
         for (int lmax = 0; lmax <= SH_LMAX && e == hipSuccess; ++lmax) {
-            for (const int ppl : {1, shk::kProjPpl<double>})
+            for (const int ppl : {1, shk::group_ppl(SH_F64, lmax, shk::kProjVecPoints)})
                 if (e == hipSuccess) e = shk::launch_group<double>(lmax, ppl, 1, s.dev, tile0, 1, s.stream);
-            for (const int ppl : {1, shk::kProjPpl<float>})
+            for (const int ppl : {1, shk::group_ppl(SH_F32, lmax, shk::kProjVecPoints)})
                 if (e == hipSuccess) e = shk::launch_group<float>(lmax, ppl, 1, s.dev, tile0, 1, s.stream);
         }
         const hipError_t w = hipStreamSynchronize(s.stream);

@@ -78,24 +78,25 @@ def test_other_kernels_vector_and_single_lanes(dev):
             assert torch.equal(fn(lmax, x, G)[1:], fn(lmax, xs, G[:, 1:].contiguous()))
 
 
+@pytest.mark.parametrize("lmax", [2, 5])
 @pytest.mark.parametrize("dt", [torch.float64, torch.float32])
-def test_projector_build_vector_and_single_lanes(dev, dt):
+def test_projector_build_vector_and_single_lanes(dev, dt, lmax):
     """Nine atoms of 120,001 to 120,009 points: together they take the launch with
-    several adjacent points per lane (more than 2^20 points; the odd sizes make
-    lanes straddle atom boundaries), each alone the one-point launch.  Every
-    atom's block is the same bit for bit."""
+    several adjacent points per lane (more than 2^20 points: 4 FP64 points at
+    lmax 2, 2 at lmax 5, 4 FP32 points; the odd sizes make lanes straddle atom
+    boundaries), each alone the one-point launch.  Every atom's block is the same
+    bit for bit."""
     rng = np.random.default_rng(21)
     sizes = [120_001 + k for k in range(9)]
     assert sum(sizes) >= 1 << 20
-    tabs = np.stack([workloads.radial_table(rng, 5, 2000, 3.0) for _ in sizes])
+    tabs = np.stack([workloads.radial_table(rng, lmax, 2000, 3.0) for _ in sizes])
     radial = sh.Radial(tabs, 3.0)
     cen = rng.uniform(0.0, 10.0, size=(len(sizes), 3))
     pts = np.concatenate([c + rng.uniform(-1.7, 1.7, size=(k, 3)) for c, k in zip(cen, sizes)])
     off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
     fn = sh.sh_projectors if dt == torch.float64 else sh.sh_projectors_f32
     c_d, p_d = torch.from_numpy(cen).to(dev, dt), torch.from_numpy(pts).to(dev, dt)
-    _say("case: projector lane identity,", sum(sizes), "points,", dt)
-    lmax = 5
+    _say("case: projector lane identity,", sum(sizes), "points, lmax", lmax, dt)
     F = (lmax + 1) ** 2
     allb = fn(lmax, c_d, torch.from_numpy(off).to(dev), p_d, radial)
     for a, k in enumerate(sizes):

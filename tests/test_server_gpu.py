@@ -236,16 +236,17 @@ def test_tiny_requests_in_a_large_group(dev, dt):
     radial.close()
 
 
-def test_alone_and_in_a_vector_group_bitwise(dev):
+@pytest.mark.parametrize("lmax", [2, 5])
+def test_alone_and_in_a_vector_group_bitwise(dev, lmax):
     """The served-alone-versus-in-the-mix identity where the lane width changes:
-    ten requests of 110,001 to 110,010 points per dtype (lmax 5) are served one at a
+    ten requests of 110,001 to 110,010 points per dtype are served one at a
     time (each its own launch, one point per lane), then all at once behind a large
     request that holds the only stream slot, so that they form one batch whose
     (dtype, lmax) groups exceed 2^20 points and take the launch with several
-    adjacent points per lane.  Each result is identical bit for bit in both runs
-    and to sh_projectors of its atom alone."""
+    adjacent points per lane (4 FP64 points at lmax 2, 2 at lmax 5, 4 FP32).  Each
+    result is identical bit for bit in both runs and to sh_projectors of its atom
+    alone."""
     rng = np.random.default_rng(14)
-    lmax = 5
     sizes = [110_001 + k for k in range(10)]
     cases = [(n, dt) for dt in ("f64", "f32") for n in sizes]
     tabs = np.stack([workloads.radial_table(rng, 9, 2000, 3.0) for _ in range(len(cases) + 1)])
