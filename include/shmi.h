@@ -227,6 +227,33 @@ int sh_projectors_f32(int lmax, int n_atoms, const float *centers, const int64_t
                       hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation: the projector
+ * build of sh_projectors / sh_projectors_f32 with the radial functions given as
+ * their knot values instead of a handle, allocating nothing.
+ *   dtype          SH_F64 or SH_F32: the type of centers, points and out
+ *   n_tables, n_r, r_max, values
+ *                  DEVICE array [n_tables][lmax+1][n_r] of double: R_l at the
+ *                  knots r_i = i r_max / (n_r - 1) (the layout sh_radial_create
+ *                  takes, with lmax + 1 channels per table)
+ *   other arguments as sh_projectors (centers, offsets, points, table_of_atom
+ *                  and out DEVICE; table_of_atom NULL means atom a uses table a).
+ * The natural-spline set-up of sh_radial_create runs on `stream` before the
+ * build, with its working arrays (the tables' (y, M) pairs, their float copy and
+ * the solve's coefficients) in a buffer the library keeps in static device memory:
+ * 64 MiB on every GPU it runs on, held until the process ends.  The results are
+ * the same, bit for bit, as sh_radial_create of the same values followed by
+ * sh_projectors (or _f32).  SH_EINVAL, with nothing launched, for the argument
+ * errors of sh_projectors and sh_radial_create and when n_tables (lmax + 1) n_r
+ * exceeds SH_NOALLOC_MAX_VALUES.  Calls that overlap on one GPU (concurrent
+ * streams or threads) share that buffer and race; order them on one stream.  The
+ * buffer keeps the last call's contents, which no call relies on. */
+#define SH_NOALLOC_MAX_VALUES (1 << 21)
+int sh_projectors_noalloc(int lmax, int dtype, int n_atoms, const void *centers, const int64_t *offsets,
+                          int64_t n_points, const void *points, int n_tables, int n_r, double r_max,
+                          const double *values, const int32_t *table_of_atom, void *out, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * Serving: continuous batching of projector requests of uneven lmax, point
  * count and dtype.  Atoms (device point sets with a centre and a radial table)
  * are registered once and stay on the device.  Each request asks for the

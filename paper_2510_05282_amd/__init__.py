@@ -28,7 +28,7 @@ __all__ = ["SH_F32", "SH_F64", "SH_LMAX", "SH_LMAX_REC", "Radial", "ShError", "S
            "sh_eval_f32", "sh_eval_grad", "sh_eval_grad_f32", "sh_eval_grad_rec", "sh_eval_grad_rec_f32",
            "sh_eval_jac", "sh_eval_ld",
            "sh_eval_rec", "sh_eval_rec_f32", "sh_eval_unit", "sh_eval_unit_f32",
-           "sh_projectors", "sh_projectors_f32", "sh_radial_create", "sh_radial_destroy",
+           "sh_projectors", "sh_projectors_f32", "sh_projectors_noalloc", "sh_radial_create", "sh_radial_destroy",
            "sh_strerror", "spherical_harmonics"]
 
 
@@ -439,6 +439,49 @@ def sh_projectors_f32(lmax: int, centers: torch.Tensor, offsets: torch.Tensor, p
     """Single-precision twin of sh_projectors (float32 centers, points, output)."""
     return _projectors("sh_projectors_f32", torch.float32, lmax, centers, offsets, points, radial,
                        table_of_atom, out, stream)
+
+
+def sh_projectors_noalloc(lmax: int, centers: torch.Tensor, offsets: torch.Tensor, points: torch.Tensor,
+                          values: torch.Tensor, r_max: float, table_of_atom: torch.Tensor | None = None,
+                          out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """The projector build from radial knot values (a float64 CUDA tensor
+    [n_tables, lmax + 1, n_r] on the uniform grid over [0, r_max]) instead of a
+    Radial handle; the library allocates nothing (its working arrays live in a
+    static device buffer).  centers, points and out are float64 or float32 (the
+    dtype of points); pass `out` to keep the call free of allocation here too."""
+    dtype = points.dtype
+    if dtype not in (torch.float64, torch.float32):
+        raise TypeError("points must be float64 or float32")
+    if (not values.is_cuda or values.dtype != torch.float64 or values.dim() != 3 or values.shape[1] != lmax + 1
+            or not values.is_contiguous()):
+        raise ValueError(f"values must be a contiguous float64 CUDA tensor [n_tables, {lmax + 1}, n_r]")
+    for name, t in (("centers", centers), ("points", points)):
+        if not t.is_cuda or t.dtype != dtype or t.dim() != 2 or t.shape[1] != 3 or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous [*, 3] {dtype} CUDA tensor")
+    n_atoms = centers.shape[0]
+    if (offsets.dtype != torch.int64 or not offsets.is_cuda or tuple(offsets.shape) != (n_atoms + 1,)
+            or not offsets.is_contiguous()):
+        raise ValueError(f"offsets must be a contiguous int64 CUDA tensor of {n_atoms + 1} entries")
+    n_points = points.shape[0]
+    F = nfun(lmax)
+    if out is None:
+        out = torch.empty(F * n_points, dtype=dtype, device=points.device)
+    elif out.dtype != dtype or out.numel() != F * n_points or not out.is_contiguous():
+        raise ValueError(f"out must be a contiguous {dtype} tensor of {F * n_points} elements")
+    toa = 0
+    if table_of_atom is not None:
+        if (table_of_atom.dtype != torch.int32 or not table_of_atom.is_cuda
+                or tuple(table_of_atom.shape) != (n_atoms,) or not table_of_atom.is_contiguous()):
+            raise ValueError("table_of_atom must be a contiguous int32 CUDA tensor of n_atoms entries")
+        toa = table_of_atom.data_ptr()
+    code = SH_F64 if dtype == torch.float64 else SH_F32
+    with torch.cuda.device(points.device):
+        check("sh_projectors_noalloc",
+              lib().sh_projectors_noalloc(lmax, code, n_atoms, centers.data_ptr(), offsets.data_ptr(), n_points,
+                                          points.data_ptr(), values.shape[0], values.shape[2], float(r_max),
+                                          values.data_ptr(), toa or None, out.data_ptr(),
+                                          _stream(points.device, stream)))
+    return out
 
 
 def sh_strerror(code: int) -> str:

@@ -81,6 +81,8 @@ def lib() -> ctypes.CDLL:
     L.sh_projectors.restype = i32
     L.sh_projectors_f32.argtypes = [i32, i32, vp, vp, i64, vp, vp, vp, vp, vp]
     L.sh_projectors_f32.restype = i32
+    L.sh_projectors_noalloc.argtypes = [i32, i32, i32, vp, vp, i64, vp, i32, i32, ctypes.c_double, vp, vp, vp, vp]
+    L.sh_projectors_noalloc.restype = i32
     u64, f64 = ctypes.c_uint64, ctypes.c_double
     L.sh_server_create.argtypes = [u64, i32, i32, ctypes.POINTER(vp)]
     L.sh_server_create_simulated.argtypes = [u64, i32, i32, f64, i32, f64, ctypes.POINTER(vp)]

@@ -4,6 +4,7 @@
 #include <stdint.h>
 
 #include <memory>
+#include <mutex>
 #include <new>
 
 #include "../../include/shmi.h"
@@ -100,6 +101,70 @@ static int grad_rec(int lmax, int64_t n, const TIO *xyz, const TIO *grad_out, TI
     if (n == 0) return SH_OK;
     if (!xyz || !grad_out || !grad_xyz) return SH_EINVAL;
     return hip_status(shk::launch_grad_rec<TIO>(lmax, n, xyz, grad_out, n, grad_xyz, stream));
+}
+
+// ---------------------------------------------------------------- no-allocation projectors
+
+// Working memory of sh_projectors_noalloc, for at most SH_NOALLOC_MAX_VALUES knot
+// values: the (y, M) pairs of the radial tables, their float copy and the spline
+// solve's eliminated coefficients (64 MiB).  Every GPU the library runs on holds
+// its own copy until the process ends; calls on one GPU share it.
+constexpr size_t kNoAllocPairs = size_t(SH_NOALLOC_MAX_VALUES) * sizeof(double2);
+constexpr size_t kNoAllocPairsF32 = size_t(SH_NOALLOC_MAX_VALUES) * sizeof(float2);
+constexpr size_t kNoAllocCoef = size_t(SH_NOALLOC_MAX_VALUES) * sizeof(double);
+static __device__ __align__(256) unsigned char scratch[kNoAllocPairs + kNoAllocPairsF32 + kNoAllocCoef];
+
+// Device address of `scratch` on each GPU, looked up once per GPU with that GPU
+// current (in host code the array's name is only a stand-in for it).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+
+int scratch_of_current_device(unsigned char** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_status(e);
+    if (dev < 0 || dev >= kMaxDevices) return SH_EINVAL;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_status(e);
+        if (!p) return hip_status(hipErrorInvalidSymbol);
+        g_scratch_ptr[dev] = p;
+    }
+    *out = static_cast<unsigned char*>(g_scratch_ptr[dev]);
+    return SH_OK;
+}
+
+template <typename TIO>
+int projectors_noalloc(int lmax, int n_atoms, const TIO* centers, const int64_t* offsets, int64_t n_points,
+                       const TIO* points, int n_tables, int n_r, double r_max, const double* values,
+                       const int32_t* table_of_atom, TIO* out, hipStream_t stream)
+{
+    unsigned char* base = nullptr;
+    const int rc = scratch_of_current_device(&base);
+    if (rc != SH_OK) return rc;
+    double2* pairs = reinterpret_cast<double2*>(base);
+    float2* pairs_f32 = reinterpret_cast<float2*>(base + kNoAllocPairs);
+    double* coef = reinterpret_cast<double*>(base + kNoAllocPairs + kNoAllocPairsF32);
+    const int ch = lmax + 1;
+    const int64_t nval = int64_t(n_tables) * ch * n_r;
+    const double h = r_max / double(n_r - 1);
+    // every entry the solve reads it writes first, so the buffer needs no clearing
+    hipError_t e = shk::launch_spline_setup(values, pairs, coef, n_tables * ch, ch, n_r, h, stream);
+    const shk::knot_t<TIO>* table;
+    if constexpr (sizeof(TIO) == 8) {
+        table = pairs;
+    } else {
+        if (e == hipSuccess) e = shk::launch_narrow_tables(pairs, pairs_f32, nval, stream);
+        table = pairs_f32;
+    }
+    if (e != hipSuccess) return hip_status(e);
+    shk::ProjArgs<TIO> A{centers, offsets, n_atoms, points, n_points, table, ch, n_tables, table_of_atom, n_r, h,
+                         r_max, out};
+    return hip_status(shk::launch_projectors<TIO>(lmax, A, stream));
 }
 
 }  // namespace
@@ -334,6 +399,26 @@ int sh_projectors_f32(int lmax, int n_atoms, const float *centers, const int64_t
 {
     return projectors<float>(lmax, n_atoms, centers, offsets, n_points, points, radial, table_of_atom, out,
                              stream);
+}
+
+int sh_projectors_noalloc(int lmax, int dtype, int n_atoms, const void *centers, const int64_t *offsets,
+                          int64_t n_points, const void *points, int n_tables, int n_r, double r_max,
+                          const double *values, const int32_t *table_of_atom, void *out, hipStream_t stream)
+{
+    if (bad_lmax(lmax) || (dtype != SH_F64 && dtype != SH_F32) || n_atoms < 0 || n_points < 0 || n_tables < 1 ||
+        n_r < 2 || !(r_max > 0.0) || !isfinite(r_max))
+        return SH_EINVAL;
+    if (int64_t(n_tables) * (lmax + 1) * n_r > SH_NOALLOC_MAX_VALUES) return SH_EINVAL;
+    if (n_points == 0) return SH_OK;
+    if (n_atoms == 0 || !centers || !offsets || !points || !values || !out) return SH_EINVAL;
+    if (!table_of_atom && n_tables < n_atoms) return SH_EINVAL;
+    if (dtype == SH_F64)
+        return projectors_noalloc<double>(lmax, n_atoms, static_cast<const double *>(centers), offsets, n_points,
+                                          static_cast<const double *>(points), n_tables, n_r, r_max, values,
+                                          table_of_atom, static_cast<double *>(out), stream);
+    return projectors_noalloc<float>(lmax, n_atoms, static_cast<const float *>(centers), offsets, n_points,
+                                      static_cast<const float *>(points), n_tables, n_r, r_max, values,
+                                      table_of_atom, static_cast<float *>(out), stream);
 }
 
 }  // extern "C"
