@@ -6,7 +6,7 @@
 // it (registers and occupancy sized for that lmax, no per-point dispatch); each
 // request is cut into tiles of 256 lanes x PPL adjacent points, evaluated with the
 // same projector code as sh_projectors (PPL as there: the vector width for a group
-// of at least kProjVecPoints points, else 1).  The groups are launched smallest
+// of at least kServeVecPoints points, else 1).  The groups are launched smallest
 // output first, each followed by an event, and progress() reports a group's
 // requests as soon as its event completes.  Request descriptors and their
 // first-tile indices travel host -> device in one copy through a pinned staging
@@ -90,10 +90,19 @@ static void launch_group_l(int ppl, int64_t tiles, const ServeDesc* descs, const
                            descs, tile0, n);
 }
 
+// Groups of at least this many points take several points per lane.  Lower than
+// the projector build's kProjVecPoints: a group is one launch of a batch, and in the
+// Poisson stream (batches of a few requests) groups of 2^18 to 2^20 points are
+// common.  Measured on the 10,000-request stream, two runs each, against 2^20: at
+// 75k req/s p50 0.18-0.19 ms (0.25-0.29), p99 1.11-1.15 ms (1.74-1.76); at 63k req/s
+// p50 0.10-0.105 ms (0.116-0.118), p99 0.67-0.71 ms (0.77-0.78); closed loop
+// unchanged within its spread (2^19: in between).
+constexpr int64_t kServeVecPoints = int64_t(1) << 18;
+
 // Lane width of a group of n points of one (dtype, lmax): 1 or kProjPpl.
 static int group_ppl(int dtype, int lmax, int64_t n)
 {
-    if (n < kProjVecPoints) return 1;
+    if (n < kServeVecPoints) return 1;
     if (dtype == SH_F32) return kProjPpl<float, 9>;  // the same for every lmax
     return lmax <= 3 ? kProjPpl<double, 3> : kProjPpl<double, 9>;
 }
@@ -318,9 +327,9 @@ private:
                                       hipMemcpyHostToDevice, s.stream);
         const int64_t* tile0 = reinterpret_cast<const int64_t*>(s.dev + 1);
         for (int lmax = 0; lmax <= SH_LMAX && e == hipSuccess; ++lmax) {
-            for (const int ppl : {1, shk::group_ppl(SH_F64, lmax, shk::kProjVecPoints)})
+            for (const int ppl : {1, shk::group_ppl(SH_F64, lmax, shk::kServeVecPoints)})
                 if (e == hipSuccess) e = shk::launch_group<double>(lmax, ppl, 1, s.dev, tile0, 1, s.stream);
-            for (const int ppl : {1, shk::group_ppl(SH_F32, lmax, shk::kProjVecPoints)})
+            for (const int ppl : {1, shk::group_ppl(SH_F32, lmax, shk::kServeVecPoints)})
                 if (e == hipSuccess) e = shk::launch_group<float>(lmax, ppl, 1, s.dev, tile0, 1, s.stream);
         }
         const hipError_t w = hipStreamSynchronize(s.stream);

@@ -205,8 +205,9 @@ def _alone(dev, lmax, center, points, radial, table):
 @pytest.mark.parametrize("dt", ["f64", "f32"])
 def test_tiny_requests_in_a_large_group(dev, dt):
     """Requests of 1 to 7 points batched with one of 2^20 + 7 points of the same
-    (dtype, lmax): the group is large enough for the launch with several adjacent
-    points per lane, so the tiny requests are single partial lanes of it.  Bit for
+    (dtype, lmax): the group is far above the 2^18 points from which a group takes the
+    launch with several adjacent points per lane, so the tiny requests are single
+    partial lanes of it.  Bit for
     bit against sh_projectors on each atom alone (the one-point launch for the tiny
     ones)."""
     rng = np.random.default_rng(13)
@@ -242,7 +243,7 @@ def test_alone_and_in_a_vector_group_bitwise(dev, lmax):
     ten requests of 110,001 to 110,010 points per dtype are served one at a
     time (each its own launch, one point per lane), then all at once behind a large
     request that holds the only stream slot, so that they form one batch whose
-    (dtype, lmax) groups exceed 2^20 points and take the launch with several
+    (dtype, lmax) groups exceed 2^18 points and take the launch with several
     adjacent points per lane (4 FP64 points at lmax 2, 2 at lmax 5, 4 FP32).  Each
     result is identical bit for bit in both runs and to sh_projectors of its atom
     alone."""
