@@ -84,6 +84,10 @@ def _parse():
                     help="no GPU work: turn the counter_collection.csv files of a --pmc FETCH_SIZE and a "
                          "--pmc WRITE_SIZE run of `--copy-probe` (and optionally a --pmc "
                          "SQ_INSTS_VALU_FLOPS_FP64 run) into the committed counter record")
+    ap.add_argument("--serving-trace-summary", metavar="CSV",
+                    help="no GPU work: split the serving kernels of a rocprofv3 kernel trace of "
+                         "`--only serving` into its passes (at idle gaps over 2 ms) and print, per pass, "
+                         "the span, how many serving kernels ran at a time, and the kernels' time")
     return ap.parse_args()
 
 
@@ -472,12 +476,62 @@ def bench_gradient(sh, workloads, dev, steps):
     return res
 
 
+def serving_trace_summary(path: str, gap_ns: int = 2_000_000) -> None:
+    """Per-pass view of a rocprofv3 kernel trace (`*_kernel_trace.csv`) of the
+    serving section: its serve_kernel dispatches (warm-up launches of one tile
+    left out) split where no serving kernel runs for more than gap_ns; for each
+    pass the dispatch count, span, the share of the span with 0, 1, 2 or 3 serving
+    kernels running, their summed duration, and the kernels with the most time."""
+    import collections
+    import csv
+    import re
+    with open(path, newline="") as fh:
+        rows = list(csv.DictReader(fh))
+
+    def grid(r):
+        return int(r.get("Grid_Size") or r.get("Grid_Size_X") or 0)
+
+    ds = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"]) for r in rows
+                if "serve_kernel" in r["Kernel_Name"] and grid(r) > 256)
+    passes, cur, end = [], [], 0
+    for d in ds:
+        if cur and d[0] - end > gap_ns:
+            passes.append(cur)
+            cur = []
+        end = d[1] if not cur else max(end, d[1])
+        cur.append(d)
+    if cur:
+        passes.append(cur)
+    for k, p in enumerate(passes):
+        t0, t1 = p[0][0], max(e for _, e, _ in p)
+        span = t1 - t0
+        ev = sorted([(s, 1) for s, _, _ in p] + [(e, -1) for _, e, _ in p])
+        at = collections.Counter()
+        c, last = 0, t0
+        for t, dlt in ev:
+            at[c] += t - last
+            c, last = c + dlt, t
+        per = collections.defaultdict(lambda: [0, 0.0])
+        for s, e, name in p:
+            m = re.search(r"serve_kernel<[^>]*>", name)
+            per[m.group(0) if m else name][0] += 1
+            per[m.group(0) if m else name][1] += (e - s) / 1e6
+        busy = sum(v[1] for v in per.values())
+        one = sum(v[1] for kk, v in per.items() if kk.endswith(", 1>"))
+        print(f"pass {k}: {len(p)} dispatches over {span / 1e6:.2f} ms; share of the span with "
+              + ", ".join(f"{n} running {at[n] / span:.3f}" for n in sorted(at))
+              + f"; kernel time {busy:.1f} ms ({one:.1f} ms in one-point-per-lane launches)")
+        for kk, v in sorted(per.items(), key=lambda kv: -kv[1][1])[:6]:
+            print(f"    {kk:30s} calls {v[0]:5d} total {v[1]:8.3f} ms avg {v[1] / v[0] * 1e3:9.1f} us")
+
+
 def bench_serving(sh, workloads, dev, n_req):
     """n_req projector requests (lmax ~ U{0..9}, n log-uniform in [1e3, 1e6], 80%
     FP64), per-atom points and radial tables (lmax + 1 channels) resident on the
     device, 64 GB budget.
-    One server for all passes.  After an untimed closed-loop pass, a closed loop
-    (everything submitted at once) gives the saturation rate; then Poisson arrivals
+    One server for all passes.  After an untimed closed-loop pass, three closed
+    loops (everything submitted at once; the median is reported) give the
+    saturation rate; then Poisson arrivals
     at 0.7x and 0.3x that rate, and at fixed 54k and 23k requests/s, give the
     latencies (rates over each pass's wall time, from its first submission to the
     end of its drain)."""
@@ -538,12 +592,15 @@ def bench_serving(sh, workloads, dev, n_req):
         return wall, st, lat
 
     run([0.0] * n_req)  # warm-up
-    wall, st, lat = run([0.0] * n_req)
+    # three closed-loop passes (each under 0.1 s): the median one is reported
+    cl = sorted((run([0.0] * n_req) for _ in range(3)), key=lambda x: x[0])
+    wall, st, lat = cl[1]
     rate = n_req / wall
     out["closed_loop"] = {"wall_s": wall, "req_per_s": rate, "points_per_s": total_points / wall,
                           "gbs": total_bytes / wall / 1e9, "batches": st["batches"],
                           "deferred": st["deferred"], "peak_bytes": st["peak_bytes"],
-                          "scheduler_cpu_frac": st["scheduler_cpu_frac"]}
+                          "scheduler_cpu_frac": st["scheduler_cpu_frac"],
+                          "passes_req_per_s": [n_req / x[0] for x in cl]}
     # Poisson arrivals at 0.7x and 0.3x the saturation rate, and at two fixed rates
     # (comparable between builds whose saturation rates differ)
     for key, lam in (("poisson", 0.7 * rate), ("poisson_0.3", 0.3 * rate), ("poisson_54k", 54000.0),
@@ -692,6 +749,9 @@ def main():
             json.dump(t, fh, indent=1)
             fh.write("\n")
         print(json.dumps(t))
+        return
+    if args.serving_trace_summary:
+        serving_trace_summary(args.serving_trace_summary)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "

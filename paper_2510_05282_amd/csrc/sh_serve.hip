@@ -8,10 +8,12 @@
 // same projector code as sh_projectors (PPL as there: the vector width for a group
 // of at least kServeVecPoints points, else 1).  The groups are launched smallest
 // output first, each followed by an event, and progress() reports a group's
-// requests as soon as its event completes.  Request descriptors and their
-// first-tile indices travel host -> device in one copy through a pinned staging
-// buffer per slot (the slot is reused only after its previous batch has completed,
-// so the staging buffer is never overwritten in flight).
+// requests as soon as its event completes.  A group of at most kInlineItems
+// requests takes its descriptors as kernel arguments; the descriptors of larger
+// groups and their first-tile indices travel host -> device in one copy per batch
+// through a pinned staging buffer per slot (the slot is reused only after its
+// previous batch has completed, so the staging buffer is never overwritten in
+// flight), and a batch with no larger group makes no copy.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
@@ -42,19 +44,37 @@ struct ServeDesc {
 
 constexpr int kServeBlock = 256;  // lanes per tile and block
 
+// Descriptors of a small group, passed by value as kernel arguments: the launch
+// needs no copy and a block finds its request among them in registers.
+constexpr int kInlineItems = 4;
+struct ServeInline {
+    ServeDesc d[kInlineItems];
+};
+
 // One launch per (lmax, dtype) group of a batch: block b handles tile
 // xcd_tile(b) of the group (the tiles of one group cost the same, so
 // XCD-contiguous ranges stay balanced and each XCD keeps few requests' tables in
-// its L2), finds its request by a wave-wide search over the group's first-tile
-// indices and evaluates P adjacent points per lane (the request's last lane
-// repeats its last point in the slots past the end and stores only its own).
+// its L2) and evaluates P adjacent points per lane (the request's last lane
+// repeats its last point in the slots past the end and stores only its own).  Its
+// request is the last of the group whose first tile is at most the block's: one of
+// the first n_items descriptors of `in` when descs is null (n_items <= kInlineItems),
+// else found by a wave-wide search over the group's first-tile indices in tile0.
 template <int LMAX, typename TIO, int P>
-__global__ __launch_bounds__(kServeBlock) void serve_kernel(const ServeDesc* __restrict__ descs,
+__global__ __launch_bounds__(kServeBlock) void serve_kernel(ServeInline in, const ServeDesc* __restrict__ descs,
                                                             const int64_t* __restrict__ tile0, int n_items)
 {
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
-    // tile0 is increasing with tile0[0] = 0 <= tile, so the search finds an item
-    const ServeDesc& d = descs[wave_search(tile0, n_items, tile)];
+    ServeDesc d;
+    if (descs == nullptr) {
+        // uniform selection without indexing the argument block by a variable
+        d = in.d[0];
+#pragma unroll
+        for (int k = 1; k < kInlineItems; ++k)
+            if (k < n_items && in.d[k].tile0 <= tile) d = in.d[k];
+    } else {
+        // tile0 is increasing with tile0[0] = 0 <= tile, so the search finds an item
+        d = descs[wave_search(tile0, n_items, tile)];
+    }
     const int64_t j = (tile - d.tile0) * (kServeBlock * P) + threadIdx.x * P;
     if (j < 0 || j >= d.n) return;
     const SplineGrid g{d.n_r, d.h, d.inv_h, d.r_max, d.h2_over_6};
@@ -79,15 +99,15 @@ __global__ __launch_bounds__(kServeBlock) void serve_kernel(const ServeDesc* __r
 }
 
 template <int LMAX, typename TIO>
-static void launch_group_l(int ppl, int64_t tiles, const ServeDesc* descs, const int64_t* tile0, int n,
-                           hipStream_t s)
+static void launch_group_l(int ppl, int64_t tiles, const ServeInline& in, const ServeDesc* descs,
+                           const int64_t* tile0, int n, hipStream_t s)
 {
     const dim3 grid = dim3(unsigned(tiles)), block = dim3(kServeBlock);
     if (ppl == 1)
-        hipLaunchKernelGGL((serve_kernel<LMAX, TIO, 1>), grid, block, 0, s, descs, tile0, n);
+        hipLaunchKernelGGL((serve_kernel<LMAX, TIO, 1>), grid, block, 0, s, in, descs, tile0, n);
     else
         hipLaunchKernelGGL((serve_kernel<LMAX, TIO, kProjPpl<TIO, LMAX>>), grid, block, (kProjCapLds<TIO, LMAX>), s,
-                           descs, tile0, n);
+                           in, descs, tile0, n);
 }
 
 // Groups of at least this many points take several points per lane.  Lower than
@@ -107,22 +127,24 @@ static int group_ppl(int dtype, int lmax, int64_t n)
     return lmax <= 3 ? kProjPpl<double, 3> : kProjPpl<double, 9>;
 }
 
-// ppl is 1 or kProjPpl<TIO, lmax>
+// ppl is 1 or kProjPpl<TIO, lmax>; descs null: the n <= kInlineItems descriptors
+// of `in`, else n descriptors at descs and their first tiles at tile0 (device)
 template <typename TIO>
-static hipError_t launch_group(int lmax, int ppl, int64_t tiles, const ServeDesc* descs, const int64_t* tile0, int n,
-                               hipStream_t s)
+static hipError_t launch_group(int lmax, int ppl, int64_t tiles, const ServeInline& in, const ServeDesc* descs,
+                               const int64_t* tile0, int n, hipStream_t s)
 {
+    if (descs == nullptr && (n < 1 || n > kInlineItems)) return hipErrorInvalidValue;
     switch (lmax) {
-    case 0: launch_group_l<0, TIO>(ppl, tiles, descs, tile0, n, s); break;
-    case 1: launch_group_l<1, TIO>(ppl, tiles, descs, tile0, n, s); break;
-    case 2: launch_group_l<2, TIO>(ppl, tiles, descs, tile0, n, s); break;
-    case 3: launch_group_l<3, TIO>(ppl, tiles, descs, tile0, n, s); break;
-    case 4: launch_group_l<4, TIO>(ppl, tiles, descs, tile0, n, s); break;
-    case 5: launch_group_l<5, TIO>(ppl, tiles, descs, tile0, n, s); break;
-    case 6: launch_group_l<6, TIO>(ppl, tiles, descs, tile0, n, s); break;
-    case 7: launch_group_l<7, TIO>(ppl, tiles, descs, tile0, n, s); break;
-    case 8: launch_group_l<8, TIO>(ppl, tiles, descs, tile0, n, s); break;
-    case 9: launch_group_l<9, TIO>(ppl, tiles, descs, tile0, n, s); break;
+    case 0: launch_group_l<0, TIO>(ppl, tiles, in, descs, tile0, n, s); break;
+    case 1: launch_group_l<1, TIO>(ppl, tiles, in, descs, tile0, n, s); break;
+    case 2: launch_group_l<2, TIO>(ppl, tiles, in, descs, tile0, n, s); break;
+    case 3: launch_group_l<3, TIO>(ppl, tiles, in, descs, tile0, n, s); break;
+    case 4: launch_group_l<4, TIO>(ppl, tiles, in, descs, tile0, n, s); break;
+    case 5: launch_group_l<5, TIO>(ppl, tiles, in, descs, tile0, n, s); break;
+    case 6: launch_group_l<6, TIO>(ppl, tiles, in, descs, tile0, n, s); break;
+    case 7: launch_group_l<7, TIO>(ppl, tiles, in, descs, tile0, n, s); break;
+    case 8: launch_group_l<8, TIO>(ppl, tiles, in, descs, tile0, n, s); break;
+    case 9: launch_group_l<9, TIO>(ppl, tiles, in, descs, tile0, n, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -239,8 +261,15 @@ public:
             }
             if (g.tiles > max_tiles()) return SH_EINVAL;
         }
-        hipError_t e = hipMemcpyAsync(s.dev, s.host, (sizeof(shk::ServeDesc) + sizeof(int64_t)) * n,
-                                      hipMemcpyHostToDevice, s.stream);
+        // groups of at most kInlineItems requests take their descriptors as arguments
+        auto items_of = [&](size_t gi) {
+            return (gi + 1 < groups_.size() ? groups_[gi + 1].first : int(n)) - groups_[gi].first;
+        };
+        bool copy = false;
+        for (size_t gi = 0; gi < groups_.size(); ++gi) copy = copy || items_of(gi) > shk::kInlineItems;
+        hipError_t e = copy ? hipMemcpyAsync(s.dev, s.host, (sizeof(shk::ServeDesc) + sizeof(int64_t)) * n,
+                                             hipMemcpyHostToDevice, s.stream)
+                            : hipSuccess;
         const int64_t* dev_tile0 = reinterpret_cast<const int64_t*>(s.dev + n);
         // smallest output first, each group's completion recorded, so the requests of
         // small groups complete without waiting for the large ones of the batch
@@ -255,11 +284,16 @@ public:
             const size_t gi = size_t(launch_order_[q]);
             const Group& g = groups_[gi];
             const int b = g.first;
-            const int m = (gi + 1 < groups_.size() ? groups_[gi + 1].first : int(n)) - b;
+            const int m = items_of(gi);
             const shk::ServeDesc& d = s.host[b];
-            e = d.dtype == SH_F64
-                    ? shk::launch_group<double>(d.lmax, g.ppl, g.tiles, s.dev + b, dev_tile0 + b, m, s.stream)
-                    : shk::launch_group<float>(d.lmax, g.ppl, g.tiles, s.dev + b, dev_tile0 + b, m, s.stream);
+            shk::ServeInline in;
+            memset(&in, 0, sizeof(in));
+            const bool inl = m <= shk::kInlineItems;
+            if (inl) memcpy(in.d, s.host + b, sizeof(shk::ServeDesc) * m);
+            const shk::ServeDesc* descs = inl ? nullptr : s.dev + b;
+            const int64_t* t0 = inl ? nullptr : dev_tile0 + b;
+            e = d.dtype == SH_F64 ? shk::launch_group<double>(d.lmax, g.ppl, g.tiles, in, descs, t0, m, s.stream)
+                                  : shk::launch_group<float>(d.lmax, g.ppl, g.tiles, in, descs, t0, m, s.stream);
             if (e == hipSuccess) e = hipEventRecord(s.group_done[q], s.stream);
             for (int k = b; k < b + m; ++k) s.group_items.push_back(order_[k]);
             s.group_end.push_back(int(s.group_items.size()));
@@ -326,11 +360,13 @@ private:
         hipError_t e = hipMemcpyAsync(s.dev, s.host, sizeof(shk::ServeDesc) + sizeof(int64_t),
                                       hipMemcpyHostToDevice, s.stream);
         const int64_t* tile0 = reinterpret_cast<const int64_t*>(s.dev + 1);
+        shk::ServeInline in;
+        memset(&in, 0, sizeof(in));
         for (int lmax = 0; lmax <= SH_LMAX && e == hipSuccess; ++lmax) {
             for (const int ppl : {1, shk::group_ppl(SH_F64, lmax, shk::kServeVecPoints)})
-                if (e == hipSuccess) e = shk::launch_group<double>(lmax, ppl, 1, s.dev, tile0, 1, s.stream);
+                if (e == hipSuccess) e = shk::launch_group<double>(lmax, ppl, 1, in, s.dev, tile0, 1, s.stream);
             for (const int ppl : {1, shk::group_ppl(SH_F32, lmax, shk::kServeVecPoints)})
-                if (e == hipSuccess) e = shk::launch_group<float>(lmax, ppl, 1, s.dev, tile0, 1, s.stream);
+                if (e == hipSuccess) e = shk::launch_group<float>(lmax, ppl, 1, in, s.dev, tile0, 1, s.stream);
         }
         const hipError_t w = hipStreamSynchronize(s.stream);
         return e != hipSuccess ? e : w;

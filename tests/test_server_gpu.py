@@ -9,7 +9,7 @@ import torch
 
 import paper_2510_05282_amd as sh
 from paper_2510_05282_amd import workloads
-from paper_2510_05282_amd.serve import DONE, SH_REQ_AUTORELEASE, Server
+from paper_2510_05282_amd.serve import DONE, RUNNING, SH_REQ_AUTORELEASE, Server
 
 pytestmark = pytest.mark.gpu
 LD = np.longdouble
@@ -274,6 +274,8 @@ def test_alone_and_in_a_vector_group_bitwise(dev, lmax):
         srv.release(t)
     b0 = srv.stats()["batches"]
     tb = srv.submit(ablk, 9)
+    while srv.poll(tb) < RUNNING:  # launched (about 2.5 ms of work): the rest queue behind it
+        pass
     tickets = [srv.submit(a, lmax) for a in atoms]
     for t in [tb] + tickets:
         assert srv.wait(t, 60) == DONE
@@ -284,6 +286,51 @@ def test_alone_and_in_a_vector_group_bitwise(dev, lmax):
         got = srv.result(t, lmax, n, torch.float64 if dt == "f64" else torch.float32)
         assert torch.equal(got, alone[k]), (k, dt)
         assert torch.equal(got.reshape(-1), _alone(dev, lmax, centers[k], dev_pts[k], radial, k)), (k, dt)
+        srv.release(t)
+    srv.release(tb)
+    srv.close()
+    radial.close()
+
+
+def test_descriptors_as_arguments_and_copied_in_one_batch(dev):
+    """One batch whose groups take their request descriptors in both ways: 4 FP64
+    lmax 3 requests of 70,000 points (the most a group passes as kernel arguments;
+    280,000 points, so several points per lane), 1 FP64 lmax 0 request of 513
+    points (arguments, one point per lane) and 5 FP32 lmax 7 requests of 1,000 to
+    3,000 points (one more than the arguments hold: copied to the device and
+    searched there).  The batch forms behind a large request that holds the only
+    stream slot; each result equals sh_projectors of its atom alone bit for bit."""
+    rng = np.random.default_rng(15)
+    cases = [(70_000, "f64", 3)] * 4 + [(513, "f64", 0)] + [(int(n), "f32", 7) for n in (1000, 1700, 2999, 3000, 2222)]
+    tabs = np.stack([workloads.radial_table(rng, 9, 2000, 3.0) for _ in range(len(cases) + 1)])
+    radial = sh.Radial(tabs, 3.0)
+    srv = Server(24 << 30, n_slots=1)
+    atoms, dev_pts, centers = [], [], []
+    for k, (n, dt, _) in enumerate(cases):
+        c = rng.uniform(0.0, 10.0, size=3).astype(np.float32 if dt == "f32" else np.float64).astype(np.float64)
+        t = torch.from_numpy(c + rng.uniform(-1.7, 1.7, size=(n, 3))).to(
+            dev, torch.float64 if dt == "f64" else torch.float32).contiguous()
+        dev_pts.append(t)
+        centers.append(c)
+        atoms.append(srv.add_atom(t, c, radial, table=k))
+    nb = 1 << 24  # the blocker: lmax 9, FP64, 12.9 GB of output
+    cb = np.array([5.0, 5.0, 5.0])
+    blk = torch.from_numpy(cb + rng.uniform(-1.7, 1.7, size=(nb, 3))).to(dev).contiguous()
+    ablk = srv.add_atom(blk, cb, radial, table=len(cases))
+    _say("case: descriptors as arguments and copied,", len(cases), "requests")
+    b0 = srv.stats()["batches"]
+    tb = srv.submit(ablk, 9)
+    while srv.poll(tb) < RUNNING:
+        pass
+    tickets = [srv.submit(a, lmax) for a, (_, _, lmax) in zip(atoms, cases)]
+    for t in [tb] + tickets:
+        assert srv.wait(t, 60) == DONE
+    batches = srv.stats()["batches"] - b0
+    _say("  batches for the blocker and the rest:", batches)
+    assert batches == 2
+    for k, (t, (n, dt, lmax)) in enumerate(zip(tickets, cases)):
+        got = srv.result(t, lmax, n, torch.float64 if dt == "f64" else torch.float32)
+        assert torch.equal(got.reshape(-1), _alone(dev, lmax, centers[k], dev_pts[k], radial, k)), (k, n, dt, lmax)
         srv.release(t)
     srv.release(tb)
     srv.close()
