@@ -333,7 +333,10 @@ int sh_server_wait(sh_server_t srv, int64_t ticket, double timeout_s, int *state
  * SH_EBUSY while the request has not finished. */
 int sh_server_result(sh_server_t srv, int64_t ticket, void **out);
 
-/* Returns a finished request's output to the budget (SH_EBUSY if not finished). */
+/* Returns a finished request's output to the budget (SH_EBUSY if not finished).
+ * The server may hand that memory to the next request's kernel as soon as this
+ * returns, on its own streams: GPU work of the caller that reads the output must
+ * have completed before the call (synchronise the stream it was queued on). */
 int sh_server_release(sh_server_t srv, int64_t ticket);
 
 /* Waits until nothing is pending, queued or running; SH_EBUSY on timeout. */

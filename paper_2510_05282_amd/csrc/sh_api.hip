@@ -12,6 +12,21 @@
 #include "sh_internal.h"
 #include "sh_server.h"
 
+// Radial tables owned by the library (opaque to C callers as `struct sh_radial`).
+struct sh_radial {
+    int lmax;      // channels per table - 1
+    int n_tables;  // tables in this handle
+    int n_r;       // knots per channel (uniform grid on [0, r_max])
+    double r_max;
+    double h;      // knot spacing r_max / (n_r - 1)
+    double2* table;      // device, [n_tables][n_r][lmax+1] of (y, M)
+    float2* table_f32;   // the same pairs rounded to float, read by the FP32 kernels
+    // for L < lmax and L <= kCompactLmax: [n_tables][n_r][L+1], the first L + 1 pairs
+    // of each row of table (and of table_f32); null otherwise
+    double2* compact[shs::kCompactLmax + 1];
+    float2* compact_f32[shs::kCompactLmax + 1];
+};
+
 namespace {
 
 thread_local int g_last_hip = 0;
@@ -86,10 +101,12 @@ static int projectors(int lmax, int n_atoms, const TIO *centers, const int64_t *
     if (n_points == 0) return SH_OK;
     if (n_atoms == 0 || !centers || !offsets || !points || !out) return SH_EINVAL;
     if (!table_of_atom && radial->n_tables < n_atoms) return SH_EINVAL;
+    // the copy with only the build's channels where the handle has one (same pairs)
+    const bool cmp = lmax < radial->lmax && lmax <= shs::kCompactLmax;
     const shk::knot_t<TIO>* table;
-    if constexpr (sizeof(TIO) == 8) table = radial->table;
-    else table = radial->table_f32;
-    shk::ProjArgs<TIO> A{centers, offsets, n_atoms, points, n_points, table, radial->lmax + 1,
+    if constexpr (sizeof(TIO) == 8) table = cmp ? radial->compact[lmax] : radial->table;
+    else table = cmp ? radial->compact_f32[lmax] : radial->table_f32;
+    shk::ProjArgs<TIO> A{centers, offsets, n_atoms, points, n_points, table, cmp ? lmax + 1 : radial->lmax + 1,
                          radial->n_tables, table_of_atom, radial->n_r, radial->h, radial->r_max, out};
     return hip_status(shk::launch_projectors<TIO>(lmax, A, stream));
 }
@@ -335,54 +352,71 @@ int sh_radial_create(int lmax, int n_tables, int n_r, double r_max, const double
     const int64_t n_ch = int64_t(n_tables) * (lmax + 1);
     const int64_t nval = n_ch * n_r;
     if (n_ch > 0x7fffffff || nval > (int64_t(1) << 34)) return SH_EINVAL;
-    double2 *table = nullptr;
-    float2 *table_f32 = nullptr;
+    std::unique_ptr<sh_radial> h(new (std::nothrow) sh_radial{});
+    if (!h) return SH_ENOMEM;
+    h->lmax = lmax;
+    h->n_tables = n_tables;
+    h->n_r = n_r;
+    h->r_max = r_max;
+    h->h = r_max / double(n_r - 1);
+    const int n_compact = lmax < shs::kCompactLmax + 1 ? lmax : shs::kCompactLmax + 1;  // L = 0 .. n_compact - 1
+    const size_t rows = size_t(n_tables) * size_t(n_r);  // knot rows over all tables
     double *y = nullptr, *scratch = nullptr;
     hipStream_t st = nullptr;
+    bool ok = hipMalloc(&h->table, sizeof(double2) * nval) == hipSuccess &&
+              hipMalloc(&h->table_f32, sizeof(float2) * nval) == hipSuccess &&
+              hipMalloc(&y, sizeof(double) * nval) == hipSuccess &&
+              hipMalloc(&scratch, sizeof(double) * nval) == hipSuccess;
+    for (int L = 0; ok && L < n_compact; ++L)
+        ok = hipMalloc(&h->compact[L], sizeof(double2) * rows * (L + 1)) == hipSuccess &&
+             hipMalloc(&h->compact_f32[L], sizeof(float2) * rows * (L + 1)) == hipSuccess;
     int rc = SH_OK;
-    hipError_t e;
-    if (hipMalloc(&table, sizeof(double2) * nval) != hipSuccess ||
-        hipMalloc(&table_f32, sizeof(float2) * nval) != hipSuccess ||
-        hipMalloc(&y, sizeof(double) * nval) != hipSuccess ||
-        hipMalloc(&scratch, sizeof(double) * nval) != hipSuccess) {
+    if (!ok) {
         (void)hipGetLastError();
         rc = SH_ENOMEM;
-        goto done;
+    } else {
+        hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipMemcpyAsync(y, host_values, sizeof(double) * nval, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            e = shk::launch_spline_setup(y, h->table, scratch, int(n_ch), lmax + 1, n_r, h->h, st);
+        if (e == hipSuccess) e = shk::launch_narrow_tables(h->table, h->table_f32, nval, st);
+        // the compact copies: the first L + 1 pairs of every knot row
+        for (int L = 0; e == hipSuccess && L < n_compact; ++L) {
+            e = shk::launch_compact_tables(h->table, h->compact[L], int64_t(rows), lmax + 1, L + 1, st);
+            if (e == hipSuccess)
+                e = shk::launch_compact_tables(h->table_f32, h->compact_f32[L], int64_t(rows), lmax + 1, L + 1, st);
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        rc = hip_status(e);
     }
-    e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipMemcpyAsync(y, host_values, sizeof(double) * nval, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess)
-        e = shk::launch_spline_setup(y, table, scratch, int(n_ch), lmax + 1, n_r, r_max / double(n_r - 1), st);
-    if (e == hipSuccess) e = shk::launch_narrow_tables(table, table_f32, nval, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    rc = hip_status(e);
-done:
     if (st) (void)hipStreamDestroy(st);
     if (y) (void)hipFree(y);
     if (scratch) (void)hipFree(scratch);
     if (rc != SH_OK) {
-        if (table) (void)hipFree(table);
-        if (table_f32) (void)hipFree(table_f32);
+        (void)sh_radial_destroy(h.release());
         return rc;
     }
-    sh_radial *h = new (std::nothrow) sh_radial{lmax, n_tables, n_r, r_max, r_max / double(n_r - 1), table,
-                                                table_f32};
-    if (!h) {
-        (void)hipFree(table);
-        (void)hipFree(table_f32);
-        return SH_ENOMEM;
-    }
-    *out = h;
+    *out = h.release();
     return SH_OK;
 }
 
 int sh_radial_destroy(sh_radial_t radial)
 {
     if (!radial) return SH_OK;
-    hipError_t e = hipFree(radial->table);
-    const hipError_t e2 = hipFree(radial->table_f32);
+    hipError_t e = hipSuccess;
+    auto release = [&](void* p) {
+        if (!p) return;
+        const hipError_t f = hipFree(p);
+        if (e == hipSuccess) e = f;
+    };
+    release(radial->table);
+    release(radial->table_f32);
+    for (int L = 0; L <= shs::kCompactLmax; ++L) {
+        release(radial->compact[L]);
+        release(radial->compact_f32[L]);
+    }
     delete radial;
-    return hip_status(e != hipSuccess ? e : e2);
+    return hip_status(e);
 }
 
 int sh_projectors(int lmax, int n_atoms, const double *centers, const int64_t *offsets, int64_t n_points,
@@ -432,6 +466,12 @@ int radial_table(sh_radial_t radial, int table, int dtype, RadialRef* out)
     const int64_t t0 = int64_t(table) * radial->n_r * (radial->lmax + 1);
     if (dtype == SH_F64) out->tab = radial->table + t0;
     else out->tab = radial->table_f32 + t0;
+    for (int L = 0; L <= kCompactLmax; ++L) {
+        const int64_t c0 = int64_t(table) * radial->n_r * (L + 1);
+        out->compact[L] = !radial->compact[L] ? nullptr
+                          : dtype == SH_F64   ? static_cast<const void*>(radial->compact[L] + c0)
+                                              : static_cast<const void*>(radial->compact_f32[L] + c0);
+    }
     out->lmax = radial->lmax;
     out->n_r = radial->n_r;
     out->h = radial->h;

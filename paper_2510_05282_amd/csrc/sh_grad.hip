@@ -28,7 +28,9 @@ constexpr int64_t kGradChunk = int64_t(1) << 28;
 // LDS reserved (not used) per workgroup of the backward kernel: at most 4 resident
 // workgroups (16 waves) per CU.  Measured on MI355X: 73% of 8 TB/s against 71.8%
 // uncapped (FP32: 74.1% against 71.0%).  Unlike the store-bound kernels, this
-// read-bound one runs best in plain workgroup order (XCD-contiguous order: 68.6%).
+// read-bound one runs best in plain workgroup order (XCD-contiguous order: 68.6%)
+// and with one point per lane: 2 adjacent points per lane (16-byte loads of G),
+// or 4 in FP32, measured 0-5% slower at lmax 3, 6 and 9 with every cap and order.
 constexpr size_t kGradCapLds = 40 * 1024;
 
 // TIO is the element type of xyz, G and the result; the normalisation and 1/r

@@ -4,17 +4,6 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-// Radial tables owned by the library (opaque to C callers as `struct sh_radial`).
-struct sh_radial {
-    int lmax;      // channels per table - 1
-    int n_tables;  // tables in this handle
-    int n_r;       // knots per channel (uniform grid on [0, r_max])
-    double r_max;
-    double h;      // knot spacing r_max / (n_r - 1)
-    double2* table;      // device, [n_tables][n_r][lmax+1] of (y, M)
-    float2* table_f32;   // the same pairs rounded to float, read by the FP32 kernels
-};
-
 namespace shk {
 
 // Knot pair type of the radial tables an FP64 or FP32 kernel reads.
@@ -89,6 +78,11 @@ hipError_t launch_projectors(int lmax, const ProjArgs<TIO>& A, hipStream_t s);
 
 // table_f32[k] = table[k] rounded to float, k < n (device arrays).
 hipError_t launch_narrow_tables(const double2* table, float2* table_f32, int64_t n, hipStream_t s);
+
+// The first ch_out pairs of each of `rows` rows of ch_in pairs: out[rows][ch_out]
+// from in[rows][ch_in] (device arrays, P = double2 or float2, 1 <= ch_out <= ch_in).
+template <typename P>
+hipError_t launch_compact_tables(const P* in, P* out, int64_t rows, int ch_in, int ch_out, hipStream_t s);
 
 // Natural-spline second derivatives for n_ch = n_tables * ch channels of n_r
 // values y[n_ch][n_r] (device): writes (y, M) pairs to table[n_tables][n_r][ch];

@@ -222,6 +222,31 @@ hipError_t launch_narrow_tables(const double2* table, float2* table_f32, int64_t
     return hipGetLastError();
 }
 
+// out[row][c] = in[row][c] for c < ch_out (rows of ch_in pairs in, ch_out out)
+template <typename P>
+__global__ void compact_tables_kernel(const P* __restrict__ in, P* __restrict__ out, int64_t rows, int ch_in,
+                                      int ch_out)
+{
+    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= rows * ch_out) return;
+    const int64_t row = k / ch_out;
+    out[k] = in[row * ch_in + (k - row * ch_out)];
+}
+
+template <typename P>
+hipError_t launch_compact_tables(const P* in, P* out, int64_t rows, int ch_in, int ch_out, hipStream_t s)
+{
+    if (rows <= 0) return hipSuccess;
+    if (ch_out < 1 || ch_out > ch_in) return hipErrorInvalidValue;
+    const int64_t n = rows * ch_out;
+    hipLaunchKernelGGL((compact_tables_kernel<P>), dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, in, out, rows,
+                       ch_in, ch_out);
+    return hipGetLastError();
+}
+
+template hipError_t launch_compact_tables<double2>(const double2*, double2*, int64_t, int, int, hipStream_t);
+template hipError_t launch_compact_tables<float2>(const float2*, float2*, int64_t, int, int, hipStream_t);
+
 hipError_t launch_spline_setup(const double* y, double2* table, double* scratch, int n_ch, int ch, int n_r,
                                double h, hipStream_t s)
 {

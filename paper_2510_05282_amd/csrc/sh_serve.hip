@@ -244,7 +244,10 @@ public:
                 memset(&d, 0, sizeof(d));
                 d.points = it.atom.points;
                 d.out = it.out;
-                d.tab = it.atom.tab;
+                // the table copy with the request's channels only, where the handle has one
+                const bool cmp = it.lmax < it.atom.tab_lmax && it.lmax <= kCompactLmax &&
+                                 it.atom.tab_compact[it.lmax] != nullptr;
+                d.tab = cmp ? it.atom.tab_compact[it.lmax] : it.atom.tab;
                 for (int q = 0; q < 3; ++q) d.c[q] = it.atom.c[q];
                 d.h = it.atom.h;
                 d.inv_h = 1.0 / it.atom.h;
@@ -254,7 +257,7 @@ public:
                 d.tile0 = g.tiles;
                 tile0[k] = g.tiles;
                 d.n_r = it.atom.n_r;
-                d.ch = it.atom.tab_lmax + 1;
+                d.ch = cmp ? it.lmax + 1 : it.atom.tab_lmax + 1;
                 d.lmax = it.lmax;
                 d.dtype = it.atom.dtype;
                 g.tiles += (it.atom.n + tp - 1) / tp;

@@ -33,13 +33,21 @@ namespace shs {
 
 using Clock = std::chrono::steady_clock;
 
+// A radial handle also keeps, for each L <= kCompactLmax below its own lmax, a copy
+// of its tables with only the first L + 1 channels: a projector build at lmax L
+// then reads each knot's pairs from a row of L + 1 pairs instead of a row of all
+// of them (fewer cache lines per lookup, a smaller table to cache).
+constexpr int kCompactLmax = 5;
+
 // The device table one atom uses: table `table` of a radial handle, in the
-// precision of dtype (SH_F64: double pairs, SH_F32: float pairs).
+// precision of dtype (SH_F64: double pairs, SH_F32: float pairs), and its copies
+// with fewer channels (compact[L]: L + 1 channels, null where the handle has none).
 struct RadialRef {
     const void* tab;
     int lmax;  // channels - 1
     int n_r;
     double h, r_max;
+    const void* compact[kCompactLmax + 1];
 };
 
 // Looks a table up in a radial handle (defined with the handles); SH_EINVAL for a
@@ -55,6 +63,7 @@ struct Atom {
     const void* tab;     // device (y, M) table of this atom's channels (double2 for FP64 atoms, float2
                          // for FP32 ones), may be null (simulation)
     int tab_lmax;        // channels - 1
+    const void* tab_compact[kCompactLmax + 1];  // the same with L + 1 channels, or null
     int n_r;
     double h, r_max;
 };

@@ -79,6 +79,7 @@ int sh_server_add_atom(sh_server_t srv, int dtype, int64_t n, const void *points
         if (rc != SH_OK) return rc;
         a.tab = t.tab;
         a.tab_lmax = t.lmax;
+        for (int L = 0; L <= shs::kCompactLmax; ++L) a.tab_compact[L] = t.compact[L];
         a.n_r = t.n_r;
         a.h = t.h;
         a.r_max = t.r_max;

@@ -103,6 +103,11 @@ class Server:
         return torch.as_tensor(_DeviceArray(self.result_ptr(ticket), (F, n), typestr), device="cuda")
 
     def release(self, ticket: int) -> None:
+        """Returns a finished request's output memory to the server, which may give
+        it to the next request's kernel at once: the work already queued on the
+        current torch stream (a clone() of the result, say) is waited for first."""
+        if torch.cuda.is_available() and torch.cuda.is_initialized():
+            torch.cuda.current_stream().synchronize()
         check("sh_server_release", lib().sh_server_release(self.handle, ticket))
 
     def drain(self, timeout_s: float = 600.0) -> None:

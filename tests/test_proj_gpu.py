@@ -148,6 +148,37 @@ def test_large_build_with_odd_atoms(dev, orc, dtype):
         assert np.abs(block.astype(LD) - want).max() <= tol, (a, j0)
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_handle_with_more_channels_than_the_build(dev, orc, dtype):
+    """A radial handle of 10 channels (lmax 9) used for builds at every lmax below
+    it (the builds at lmax <= 5 read the handle's copies holding only their own
+    channels): each build is bit for bit the build from a handle of exactly
+    lmax + 1 channels of the same values, on a small build (one point per lane) and
+    on a build of over 2^20 points (several points per lane); the small builds also
+    match the oracle."""
+    A = workloads.atom_spheres(seed=3, n_atoms=3, radius=1.5, h=0.25, lmax=9, n_r=300)
+    if dtype == torch.float32:
+        A.points = A.points.astype(np.float32).astype(np.float64)
+        A.centers = A.centers.astype(np.float32).astype(np.float64)
+    rng = np.random.default_rng(78)
+    sizes = [300_001, 299_999, 262_147, 250_000]
+    centers = rng.uniform(0.0, 5.0, size=(len(sizes), 3))
+    pts = np.concatenate([c + rng.uniform(-1.7, 1.7, size=(k, 3)) for c, k in zip(centers, sizes)])
+    offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    tables = np.stack([workloads.radial_table(rng, 9, 300, 3.0) for _ in sizes])
+    B = workloads.AtomSet(9, centers, offsets, pts, tables, 3.0)
+    tol = 1e-13 if dtype == torch.float64 else 5e-6
+    for lmax in range(9):
+        _say("case: 10-channel handle, build at lmax", lmax, dtype)
+        got = _run(dev, lmax, A, dtype)
+        assert np.array_equal(got, _run(dev, lmax, A, dtype, tables=np.ascontiguousarray(A.tables[:, : lmax + 1])))
+        ref = orc.projectors(lmax, A.centers, A.offsets, A.points, A.tables[:, : lmax + 1], A.r_max)
+        assert np.abs(got.astype(LD) - ref).max() <= tol
+        if lmax in (0, 1, 3, 5, 6):
+            big = _run(dev, lmax, B, dtype)
+            assert np.array_equal(big, _run(dev, lmax, B, dtype, tables=np.ascontiguousarray(tables[:, : lmax + 1])))
+
+
 def test_unit_radial_is_plain_eval(dev):
     """With R_l = 1 the projector is the plain harmonics of p - c.  The two kernels
     evaluate the same polynomials in different code (the projector on vectors of

@@ -337,6 +337,43 @@ def test_descriptors_as_arguments_and_copied_in_one_batch(dev):
     radial.close()
 
 
+def test_release_waits_for_the_callers_stream(dev):
+    """The server may give a released output's memory to the next request at once,
+    on its own stream; the Python binding's release() first waits for the work
+    queued on the current torch stream.  A clone() of a result queued behind about
+    a millisecond of other work, then release() and a request that reuses the same
+    memory: the clone holds the finished result, bit for bit."""
+    rng = np.random.default_rng(16)
+    lmax, n = 6, 100_000
+    tabs = np.stack([workloads.radial_table(rng, lmax, 2000, 3.0) for _ in range(2)])
+    radial = sh.Radial(tabs, 3.0)
+    srv = Server(1 << 30, n_slots=1)
+    atoms = []
+    for k in range(2):
+        c = rng.uniform(0.0, 10.0, size=3)
+        t = torch.from_numpy(c + rng.uniform(-1.7, 1.7, size=(n, 3))).to(dev).contiguous()
+        atoms.append((srv.add_atom(t, c, radial, table=k), t))
+    _say("case: release after a clone queued behind other work")
+    ta = srv.submit(atoms[0][0], lmax)
+    assert srv.wait(ta, 60) == DONE
+    ref = srv.result(ta, lmax, n, torch.float64).clone()
+    torch.cuda.synchronize()
+    ptr = srv.result_ptr(ta)
+    busy = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+    for _ in range(4):
+        busy.fill_(1.0)  # about 1 GB written per fill
+    late = srv.result(ta, lmax, n, torch.float64).clone()
+    srv.release(ta)
+    tb = srv.submit(atoms[1][0], lmax)
+    assert srv.wait(tb, 60) == DONE
+    assert srv.result_ptr(tb) == ptr  # the second request took the released memory
+    torch.cuda.synchronize()
+    assert torch.equal(late, ref)
+    srv.release(tb)
+    srv.close()
+    radial.close()
+
+
 def test_full_workload_sampled(dev, orc):
     """The serving benchmark's workload at full size and in its launch
     configuration: 10,000 requests (lmax U{0..9}, n log-uniform in [1e3, 1e6], 80%
