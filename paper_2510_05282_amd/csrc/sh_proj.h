@@ -205,22 +205,25 @@ __device__ __forceinline__ void proj_points(const double (&px)[PPL], const doubl
 }
 
 // Lane width of the projector and serving launches.  Several adjacent points per
-// lane (two FP64 at lmax >= 4, four FP64 below, four FP32: row stores of 16 bytes
-// or more) raise the throughput of a launch that fills the GPU many times over
-// (measured on 64 x 150k-point builds: +35% at lmax 6 in FP64, +10-21% at lmax 3-9
-// in FP32; four FP64 points instead of two: +5-17% at lmax 0-3 with the LDS cap
-// below, -7% at lmax 6; eight: slower everywhere), but lengthen each workgroup,
-// which is what a launch too small to fill the GPU waits for; launches below
-// kProjVecPoints points keep one point per lane.
-template <typename TIO, int LMAX> constexpr int kProjPpl = sizeof(TIO) == 8 ? (LMAX <= 3 ? 4 : 2) : 4;
+// lane (row stores of 16 bytes or more) raise the throughput of a launch that
+// fills the GPU many times over, but lengthen each workgroup, which is what a
+// launch too small to fill the GPU waits for; launches below kProjVecPoints points
+// keep one point per lane.  The widths, and the LDS reservation below, were chosen
+// per (dtype, lmax) on 64 x 150k-point builds from tables of lmax + 1 channels:
+// FP64 four points at lmax 1-2, two elsewhere (lmax 0: 45% of 8 TB/s against 42%
+// with four and the reservation; lmax 3: 56% against 53-54%; lmax 1-2: 46 / 51%
+// against 44 / 50% with two; lmax >= 4: two, +35% at lmax 6 over one, four 7-10%
+// slower); FP32 four (+10-21% at lmax 3-9 over one; two or eight no faster).
+template <typename TIO, int LMAX> constexpr int kProjPpl = sizeof(TIO) == 4 ? 4 : (LMAX == 1 || LMAX == 2 ? 4 : 2);
 constexpr int64_t kProjVecPoints = int64_t(1) << 20;
 
 // LDS reserved (not used) by the launches with several points per lane: at most 2
 // resident workgroups per CU, which keeps each row's concurrent writes in a
-// smaller window (as for the forward kernel).  Measured on 64 x 150k-point builds:
-// FP64 +1-13% (lmax 0-9, with 4 points per lane at lmax <= 3), FP32 +5-12% at
-// lmax >= 2, -1-2% at lmax 0-1 (no cap there).
-template <typename TIO, int LMAX> constexpr size_t kProjCapLds = (sizeof(TIO) == 4 && LMAX <= 1) ? 0 : 54 * 1024;
+// smaller window (as for the forward kernel).  Measured on the same builds: +1-13%
+// at FP64 lmax 1-9 and FP32 lmax >= 2; FP64 lmax 0 and FP32 lmax 0-1 run faster
+// without it (the FP64 lmax 0 launch with two points per lane: 45% against 34%).
+template <typename TIO, int LMAX>
+constexpr size_t kProjCapLds = (sizeof(TIO) == 4 ? LMAX <= 1 : LMAX == 0) ? 0 : 54 * 1024;
 
 // Lane width of a launch of n points.
 template <typename TIO, int LMAX> constexpr int proj_ppl(int64_t n) { return n >= kProjVecPoints ? kProjPpl<TIO, LMAX> : 1; }

@@ -120,11 +120,17 @@ static void launch_group_l(int ppl, int64_t tiles, const ServeInline& in, const 
 constexpr int64_t kServeVecPoints = int64_t(1) << 18;
 
 // Lane width of a group of n points of one (dtype, lmax): 1 or kProjPpl.
+template <typename TIO, int... L>
+static int vec_ppl_of(int lmax, std::integer_sequence<int, L...>)
+{
+    constexpr int w[] = {kProjPpl<TIO, L>...};
+    return w[lmax];
+}
 static int group_ppl(int dtype, int lmax, int64_t n)
 {
     if (n < kServeVecPoints) return 1;
-    if (dtype == SH_F32) return kProjPpl<float, 9>;  // the same for every lmax
-    return lmax <= 3 ? kProjPpl<double, 3> : kProjPpl<double, 9>;
+    return dtype == SH_F32 ? vec_ppl_of<float>(lmax, std::make_integer_sequence<int, SH_LMAX + 1>{})
+                           : vec_ppl_of<double>(lmax, std::make_integer_sequence<int, SH_LMAX + 1>{});
 }
 
 // ppl is 1 or kProjPpl<TIO, lmax>; descs null: the n <= kInlineItems descriptors
