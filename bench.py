@@ -88,6 +88,14 @@ def _parse():
                     help="no GPU work: split the serving kernels of a rocprofv3 kernel trace of "
                          "`--only serving` into its passes (at idle gaps over 2 ms) and print, per pass, "
                          "the span, how many serving kernels ran at a time, and the kernels' time")
+    ap.add_argument("--counter-summary", nargs="+", metavar="CSV",
+                    help="no GPU work: mean of each counter per dispatch over each run of consecutive "
+                         "dispatches of one kernel and grid size, from the counter_collection.csv files of "
+                         "rocprofv3 --pmc passes over the same command (one markdown row per run)")
+    ap.add_argument("--counter-chunk", type=int, default=0,
+                    help="with --counter-summary: cut each run into chunks of this many dispatches")
+    ap.add_argument("--counter-kernels", default="",
+                    help="with --counter-summary: comma-separated substrings; only kernels that contain one")
     return ap.parse_args()
 
 
@@ -476,6 +484,53 @@ def bench_gradient(sh, workloads, dev, steps):
     return res
 
 
+def counter_summary(paths, chunk: int = 0, kernels: str = "") -> None:
+    """Counters of several rocprofv3 --pmc passes over one command, side by side.
+    Each file's dispatches (in order) are cut into runs of consecutive dispatches
+    with the same kernel and grid size (and into chunks of `chunk` dispatches when
+    given); the passes ran the same program, so run k of every file is the same
+    work, and each row gives the mean per dispatch of every counter of every pass."""
+    import csv
+    import re
+    keep = [k for k in kernels.split(",") if k]
+    table, names, order = {}, [], []
+    for path in paths:
+        disp = {}
+        with open(path, newline="") as fh:
+            for r in csv.DictReader(fh):
+                d = disp.setdefault(int(r["Dispatch_Id"]), {"kernel": r["Kernel_Name"], "grid": int(r["Grid_Size"]),
+                                                            "vgpr": r.get("VGPR_Count", ""), "c": {}})
+                d["c"][r["Counter_Name"]] = d["c"].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        runs = []
+        for i in sorted(disp):
+            d = disp[i]
+            if keep and not any(k in d["kernel"] for k in keep):
+                continue
+            key = (d["kernel"], d["grid"])
+            if not runs or runs[-1]["key"] != key or (chunk and len(runs[-1]["ids"]) == chunk):
+                runs.append({"key": key, "ids": [], "vgpr": d["vgpr"], "c": {}})
+            runs[-1]["ids"].append(i)
+            for n, v in d["c"].items():
+                runs[-1]["c"].setdefault(n, []).append(v)
+        for k, run in enumerate(runs):
+            row = table.setdefault(k, {"key": run["key"], "n": len(run["ids"]), "vgpr": run["vgpr"], "c": {}})
+            if row["key"] != run["key"]:
+                raise SystemExit(f"{path}: run {k} is {run['key']}, other passes have {row['key']}")
+            for n, v in run["c"].items():
+                row["c"][n] = sum(v) / len(v)
+                if n not in names:
+                    names.append(n)
+        order = sorted(table)
+    short = lambda name: re.sub(r"\((?!anon)[^()]*\)$", "", name.replace("void ", "")
+                                .replace("(anonymous namespace)::", "")).strip()
+    print("| run | kernel | grid | dispatches | VGPRs | " + " | ".join(names) + " |")
+    print("|" + "---|" * (5 + len(names)))
+    for k in order:
+        row = table[k]
+        print(f"| {k} | {short(row['key'][0])} | {row['key'][1]} | {row['n']} | {row['vgpr']} | "
+              + " | ".join(f"{row['c'][n]:.6g}" if n in row["c"] else "" for n in names) + " |")
+
+
 def serving_trace_summary(path: str, gap_ns: int = 2_000_000) -> None:
     """Per-pass view of a rocprofv3 kernel trace (`*_kernel_trace.csv`) of the
     serving section: its serve_kernel dispatches (warm-up launches of one tile
@@ -749,6 +804,9 @@ def main():
             json.dump(t, fh, indent=1)
             fh.write("\n")
         print(json.dumps(t))
+        return
+    if args.counter_summary:
+        counter_summary(args.counter_summary, args.counter_chunk, args.counter_kernels)
         return
     if args.serving_trace_summary:
         serving_trace_summary(args.serving_trace_summary)
