@@ -179,7 +179,6 @@ public:
             for (hipEvent_t& ev : s.group_done)
                 events_ok = events_ok && hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess;
             if (!events_ok || hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||
-                hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess ||
                 hipHostMalloc(reinterpret_cast<void**>(&s.host), kSlotBytes) != hipSuccess ||
                 hipMalloc(&s.dev, kSlotBytes) != hipSuccess) {
                 (void)hipGetLastError();
@@ -198,7 +197,6 @@ public:
             if (s.stream) (void)hipStreamSynchronize(s.stream);
             if (s.dev) (void)hipFree(s.dev);
             if (s.host) (void)hipHostFree(s.host);
-            if (s.done) (void)hipEventDestroy(s.done);
             for (hipEvent_t ev : s.group_done)
                 if (ev) (void)hipEventDestroy(ev);
             if (s.stream) (void)hipStreamDestroy(s.stream);
@@ -307,7 +305,6 @@ public:
             for (int k = b; k < b + m; ++k) s.group_items.push_back(order_[k]);
             s.group_end.push_back(int(s.group_items.size()));
         }
-        if (e == hipSuccess) e = hipEventRecord(s.done, s.stream);
         if (e != hipSuccess) {
             // groups launched before the failure may still be writing into outputs the
             // scheduler is about to release: let them finish first
@@ -317,9 +314,13 @@ public:
         return SH_OK;
     }
 
+    // The batch's last launch is its last group's, followed by that group's event:
+    // the batch is complete when that event is.
     int query(int slot) override
     {
-        const hipError_t e = hipEventQuery(slots_[slot].done);
+        const Slot& s = slots_[slot];
+        if (s.group_end.empty()) return 1;
+        const hipError_t e = hipEventQuery(s.group_done[s.group_end.size() - 1]);
         if (e == hipSuccess) return 1;
         if (e == hipErrorNotReady) return 0;
         return -1;
@@ -337,7 +338,7 @@ public:
                 done.push_back(s.group_items[i]);
             ++s.next;
         }
-        return query(slot);
+        return 1;  // every group's event has completed, the last one included
     }
 
 private:
@@ -348,7 +349,6 @@ private:
     static constexpr int kMaxGroups = 2 * (SH_LMAX + 1);
     struct Slot {
         hipStream_t stream = nullptr;
-        hipEvent_t done = nullptr;
         std::vector<hipEvent_t> group_done;  // recorded after each launch of a batch, in launch order
         std::vector<int> group_items;        // the batch's item indices, group by group in launch order
         std::vector<int> group_end;          // end of each group's items in group_items
