@@ -6,7 +6,13 @@
 // flops, so it is bound by HBM stores.  Launch choices, all measured on MI355X:
 //  - Each lane evaluates 16 bytes' worth of adjacent points (two in FP64, four
 //    in FP32) and stores 16 bytes per row: one contiguous 1 KiB run per wave and
-//    row.  Outputs whose rows are not 16-byte aligned take the one-point kernel.
+//    row.  Outputs whose rows are not 16-byte aligned take the one-point kernel,
+//    and so do calls of fewer than kFwdVecPoints points: a launch that leaves CUs
+//    idle lasts as long as one workgroup's chain of work, which the wider lanes
+//    lengthen (kernel trace, lmax 9, 4k / 16k / 64k / 100k points: FP64 5.4 / 6.8 /
+//    10.1 / 14.0 us with one point per lane against 6.6 / 8.1 / 10.6 / 14.1 with
+//    two, FP32 4.2 / 4.8 / 7.1 / 9.1 against 7.6 / 8.4 / 10.0 / 10.4 with four;
+//    equal at 2^18 points, the wide lanes ahead above).
 //  - Workgroups are remapped so each XCD walks one contiguous range of points.
 //  - The 16-byte kernels reserve LDS they do not use, which caps the resident
 //    workgroups per CU at 2 (8 waves).  Fewer points in flight keep the
@@ -24,6 +30,9 @@ namespace shk {
 // Points per launch: keeps every per-row byte offset of a launch below 2^31 so
 // the store address is a scalar row base plus a 32-bit per-lane offset.
 constexpr int64_t kChunk = int64_t(1) << 28;
+
+// Calls of at least this many points take the 16-byte lanes.
+constexpr int64_t kFwdVecPoints = int64_t(1) << 18;
 
 // LDS reserved (not used) per 256-thread workgroup of the 16-byte kernels: more
 // than a third of the CU's 160 KiB, so at most 2 workgroups are resident per CU.
@@ -55,7 +64,8 @@ template <int LMAX, typename TIO, In MODE>
 static hipError_t launch_fwd_l(int64_t n, Inputs<MODE, TIO> in, TIO* out, int64_t ld, hipStream_t s)
 {
     constexpr int kVec = 16 / sizeof(TIO);
-    const bool vec_ok = ld % kVec == 0 && reinterpret_cast<uintptr_t>(out) % (kVec * sizeof(TIO)) == 0;
+    const bool vec_ok = n >= kFwdVecPoints && ld % kVec == 0 &&
+                        reinterpret_cast<uintptr_t>(out) % (kVec * sizeof(TIO)) == 0;
     for (int64_t c0 = 0; c0 < n; c0 += kChunk) {
         const int64_t nc = n - c0 < kChunk ? n - c0 : kChunk;
         hipError_t e;

@@ -72,8 +72,10 @@ def test_every_lmax(dev, orc):
         assert np.abs(got32.astype(LD) - ref32).max() <= TOL32
 
 
-@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 255, 256, 257, 1000, 4097])
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 255, 256, 257, 1000, 4097, (1 << 18) - 1, (1 << 18) + 1])
 def test_ragged_sizes(dev, orc, n):
+    """Below 2^18 points one point per lane; from 2^18 on two, with a one-point
+    launch for an odd last point."""
     _say("case: ragged n =", n)
     pts = workloads.isotropic_points(n, 0.1, 5.0, seed=100 + n)
     x = torch.from_numpy(pts).to(dev)
@@ -84,9 +86,11 @@ def test_ragged_sizes(dev, orc, n):
     assert np.abs(got.astype(LD) - orc.eval_xyz(9, pts)).max() <= TOL64
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 5, 6, 7, 63, 65, 257, 1001, 4099])
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 6, 7, 63, 65, 257, 1001, 4099, (1 << 18) - 1, (1 << 18) + 1,
+                               (1 << 18) + 2, (1 << 18) + 3])
 def test_ragged_sizes_fp32(dev, orc, n):
-    """FP32 runs four points per lane: remainders of 1-3 points take a second launch."""
+    """FP32 runs four points per lane from 2^18 points on: remainders of 1-3 points
+    take a second launch; smaller calls run one point per lane."""
     pts = workloads.isotropic_points(n, 0.1, 5.0, seed=200 + n).astype(np.float32)
     x = torch.from_numpy(pts).to(dev)
     out = torch.full((100, n), float("nan"), dtype=torch.float32, device=dev)

@@ -37,11 +37,13 @@ def _pts(n, seed, dtype, dev):
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_real_harmonics_vector_and_single_lanes(dev, dtype):
-    """n = 4k + 1 points: the main launch takes 16 bytes of points per lane and the
-    last point goes through the one-point launch; an output with an odd row stride
-    sends every point through the one-point launch; the batch without its first
-    point is a whole number of vectors.  All three agree bit for bit."""
-    n = 40001
+    """n = 2^18 + 1 points: the main launch takes 16 bytes of points per lane and
+    the last point goes through the one-point launch; an output with an odd row
+    stride sends every point through the one-point launch; the batch without its
+    first point is a whole number of vectors (2^18, the smallest call that takes
+    them), and the 2^18 - 1 points after its first point run one point per lane.
+    All agree bit for bit."""
+    n = (1 << 18) + 1
     x = _pts(n, 1, dtype, dev)
     fn = sh.sh_eval if dtype == torch.float64 else sh.sh_eval_f32
     for lmax in (2, 6, 9):
@@ -52,6 +54,7 @@ def test_real_harmonics_vector_and_single_lanes(dev, dtype):
         one = sh.sh_eval_ld(lmax, x, wide[:, :n])
         assert torch.equal(y, one)
         assert torch.equal(y[:, 1:], fn(lmax, x[1:].contiguous()))
+        assert torch.equal(y[:, 2:], fn(lmax, x[2:].contiguous()))
 
 
 def test_other_kernels_vector_and_single_lanes(dev):
