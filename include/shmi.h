@@ -266,9 +266,9 @@ int sh_projectors_noalloc(int lmax, int dtype, int n_atoms, const void *centers,
  * on the device until released.  Within a batch the groups run smallest output
  * first and each request completes when its group does.  A request's latency is
  * measured from sh_server_submit to the host seeing its group complete.  Creation
- * also runs
- * every serving kernel once on an empty request, so that no first launch (which
- * is slow) falls in the middle of serving.  Every function is thread-safe.
+ * also runs every serving kernel once on an empty request, so that no first
+ * launch (which is slow) falls in the middle of serving.  Every function is
+ * thread-safe.
  */
 typedef struct sh_server *sh_server_t;
 
