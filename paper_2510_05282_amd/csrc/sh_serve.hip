@@ -1,19 +1,22 @@
-// sh_serve.hip -- HIP executor of the projector server: one batched kernel per
-// batch on one of n_slots streams.
+// sh_serve.hip -- HIP executor of the projector server: the launches of a batch on
+// one of n_slots streams.
 //
 // A batch is a list of requests of any lmax and either dtype.  The requests are
-// grouped by (dtype, lmax) and each group gets one launch of the kernel built for
-// it (registers and occupancy sized for that lmax, no per-point dispatch); each
-// request is cut into tiles of 256 lanes x PPL adjacent points, evaluated with the
-// same projector code as sh_projectors (PPL as there: the vector width for a group
-// of at least kServeVecPoints points, else 1).  The groups are launched smallest
-// output first, each followed by an event, and progress() reports a group's
-// requests as soon as its event completes.  A group of at most kInlineItems
-// requests takes its descriptors as kernel arguments; the descriptors of larger
-// groups and their first-tile indices travel host -> device in one copy per batch
-// through a pinned staging buffer per slot (the slot is reused only after its
-// previous batch has completed, so the staging buffer is never overwritten in
-// flight), and a batch with no larger group makes no copy.
+// grouped by (dtype, lmax); each request is cut into tiles of 256 lanes x PPL
+// adjacent points, evaluated with the same projector code as sh_projectors (PPL as
+// there: the vector width for a group of at least kServeVecPoints points, else 1).
+// Each vector-width group gets one launch of the kernel built for it (registers and
+// occupancy sized for that lmax, no per-point dispatch); the one-point groups share
+// one launch of the mixed kernel when there are two or more of them (a block runs
+// the code of its request's (dtype, lmax)), which saves the host a launch and an
+// event per extra group.  The launches go smallest output first, each followed by
+// an event, and progress() reports a launch's requests as soon as its event
+// completes.  A launch of at most kInlineItems requests takes their descriptors as
+// kernel arguments; the descriptors of larger launches and their first-tile
+// indices travel host -> device in one copy per batch through a pinned staging
+// buffer per slot (the slot is reused only after its previous batch has completed,
+// so the staging buffer is never overwritten in flight), and a batch with no
+// larger launch makes no copy.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
@@ -51,20 +54,13 @@ struct ServeInline {
     ServeDesc d[kInlineItems];
 };
 
-// One launch per (lmax, dtype) group of a batch: block b handles tile
-// xcd_tile(b) of the group (the tiles of one group cost the same, so
-// XCD-contiguous ranges stay balanced and each XCD keeps few requests' tables in
-// its L2) and evaluates P adjacent points per lane (the request's last lane
-// repeats its last point in the slots past the end and stores only its own).  Its
-// request is the last of the group whose first tile is at most the block's: one of
-// the first n_items descriptors of `in` when descs is null (n_items <= kInlineItems),
-// else found by a wave-wide search over the group's first-tile indices in tile0.
-template <int LMAX, typename TIO, int P>
-__global__ __launch_bounds__(kServeBlock) void serve_kernel(ServeInline in, const ServeDesc* __restrict__ descs,
-                                                            const int64_t* __restrict__ tile0, int n_items)
+// The descriptor of a launch's tile: the last of the launch's n_items requests whose
+// first tile is at most `tile`, one of the first n_items descriptors of `in` when
+// descs is null (n_items <= kInlineItems), else found by a wave-wide search over
+// their first-tile indices in tile0.
+__device__ __forceinline__ void find_desc(const ServeInline& in, const ServeDesc* __restrict__ descs,
+                                          const int64_t* __restrict__ tile0, int n_items, int64_t tile, ServeDesc& d)
 {
-    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
-    ServeDesc d;
     if (descs == nullptr) {
         // uniform selection without indexing the argument block by a variable
         d = in.d[0];
@@ -75,13 +71,45 @@ __global__ __launch_bounds__(kServeBlock) void serve_kernel(ServeInline in, cons
         // tile0 is increasing with tile0[0] = 0 <= tile, so the search finds an item
         d = descs[wave_search(tile0, n_items, tile)];
     }
+}
+
+// Point j of request d, one point per lane.
+template <int LMAX, typename TIO>
+__device__ __forceinline__ void serve_point(const ServeDesc& d, int64_t j, const SplineGrid& g)
+{
+    const TIO* p = static_cast<const TIO*>(d.points) + 3 * j;
+    proj_point<LMAX, TIO>(double(p[0]), double(p[1]), double(p[2]), d.c, static_cast<const knot_t<TIO>*>(d.tab),
+                          d.ch, g, static_cast<TIO*>(d.out) + j, d.n);
+}
+
+// One launch per (lmax, dtype) group of a batch: block b handles tile
+// xcd_tile(b) of the group (the tiles of one group cost the same, so
+// XCD-contiguous ranges stay balanced and each XCD keeps few requests' tables in
+// its L2) and evaluates P adjacent points per lane (the request's last lane
+// repeats its last point in the slots past the end and stores only its own).
+template <int LMAX, typename TIO, int P>
+__global__ __launch_bounds__(kServeBlock) void serve_kernel(ServeInline in, const ServeDesc* __restrict__ descs,
+                                                            const int64_t* __restrict__ tile0, int n_items)
+{
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    // as find_desc, written out: through a reference to the argument block the
+    // compiler allocated this kernel's registers differently (104 VGPRs and 56
+    // SGPRs against 122 and 40 at lmax 9, FP64), and the serving closed loop ran
+    // 1.2% slower
+    ServeDesc d;
+    if (descs == nullptr) {
+        d = in.d[0];
+#pragma unroll
+        for (int k = 1; k < kInlineItems; ++k)
+            if (k < n_items && in.d[k].tile0 <= tile) d = in.d[k];
+    } else {
+        d = descs[wave_search(tile0, n_items, tile)];
+    }
     const int64_t j = (tile - d.tile0) * (kServeBlock * P) + threadIdx.x * P;
     if (j < 0 || j >= d.n) return;
     const SplineGrid g{d.n_r, d.h, d.inv_h, d.r_max, d.h2_over_6};
     if constexpr (P == 1) {
-        const TIO* p = static_cast<const TIO*>(d.points) + 3 * j;
-        proj_point<LMAX, TIO>(double(p[0]), double(p[1]), double(p[2]), d.c,
-                              static_cast<const knot_t<TIO>*>(d.tab), d.ch, g, static_cast<TIO*>(d.out) + j, d.n);
+        serve_point<LMAX, TIO>(d, j, g);
     } else {
         const int nvalid = d.n - j < P ? int(d.n - j) : P;
         const TIO* p = static_cast<const TIO*>(d.points) + 3 * j;
@@ -96,6 +124,37 @@ __global__ __launch_bounds__(kServeBlock) void serve_kernel(ServeInline in, cons
         proj_points<LMAX, TIO, P>(px, py, pz, d.c, static_cast<const knot_t<TIO>*>(d.tab), d.ch, g,
                                   static_cast<TIO*>(d.out) + j, d.n, nvalid);
     }
+}
+
+// The one-point-per-lane groups of a batch in one launch: requests of any lmax and
+// either dtype, each block running the code of its request's (dtype, lmax) (the
+// same code as serve_kernel<LMAX, TIO, 1>, so a value does not depend on which
+// launch computed it).
+__global__ __launch_bounds__(kServeBlock) void serve_mixed_kernel(ServeInline in,
+                                                                   const ServeDesc* __restrict__ descs,
+                                                                   const int64_t* __restrict__ tile0, int n_items)
+{
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    ServeDesc d;
+    find_desc(in, descs, tile0, n_items, tile, d);
+    const int64_t j = (tile - d.tile0) * kServeBlock + threadIdx.x;
+    if (j < 0 || j >= d.n) return;
+    const SplineGrid g{d.n_r, d.h, d.inv_h, d.r_max, d.h2_over_6};
+    static_for<0, SH_LMAX + 1>([&](auto lc) {
+        constexpr int L = decltype(lc)::value;
+        if (d.lmax == L) {
+            if (d.dtype == SH_F64) serve_point<L, double>(d, j, g);
+            else serve_point<L, float>(d, j, g);
+        }
+    });
+}
+
+static hipError_t launch_mixed(int64_t tiles, const ServeInline& in, const ServeDesc* descs, const int64_t* tile0,
+                               int n, hipStream_t s)
+{
+    if (descs == nullptr && (n < 1 || n > kInlineItems)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(serve_mixed_kernel, dim3(unsigned(tiles)), dim3(kServeBlock), 0, s, in, descs, tile0, n);
+    return hipGetLastError();
 }
 
 template <int LMAX, typename TIO>
@@ -217,32 +276,45 @@ public:
         if (items.empty()) return SH_OK;
         Slot& s = slots_[slot];
         const size_t n = items.size();
-        // items grouped by (dtype, lmax), in arrival order within a group
+        // items grouped by (dtype, lmax), in arrival order within a group; each
+        // group's lane width from its size (keys: dtype * 16 + lmax)
+        auto key = [&](int k) { return items[k].atom.dtype * 16 + items[k].lmax; };
+        int64_t points_of[32] = {};
+        for (size_t k = 0; k < n; ++k) points_of[key(int(k))] += items[k].atom.n;
+        int ppl_of[32];
+        int n_small = 0;           // groups with one point per lane
+        int64_t small_points = 0;  // and their points
+        for (int c = 0; c < 32; ++c) {
+            ppl_of[c] = points_of[c] ? shk::group_ppl(c / 16, c % 16, points_of[c]) : 0;
+            n_small += ppl_of[c] == 1;
+            small_points += ppl_of[c] == 1 ? points_of[c] : 0;
+        }
+        // the one-point groups first, then the vector-lane groups; two or more
+        // one-point groups of fewer than kServeVecPoints points together form one
+        // launch (the mixed kernel): one launch and one event on the host instead
+        // of one per group.  Larger sets keep their own kernels, whose registers are
+        // sized for their lmax (the mixed kernel's for the largest).
+        const bool merge = n_small >= 2 && small_points < shk::kServeVecPoints;
         order_.resize(n);
         for (size_t k = 0; k < n; ++k) order_[k] = int(k);
-        auto key = [&](int k) { return items[k].atom.dtype * 16 + items[k].lmax; };
-        std::stable_sort(order_.begin(), order_.end(), [&](int a, int b) { return key(a) < key(b); });
-        // groups (first item, points), then the lane width of each from its size
-        groups_.clear();
+        auto rank = [&](int k) { return (ppl_of[key(k)] > 1 ? 64 : 0) + key(k); };
+        std::stable_sort(order_.begin(), order_.end(), [&](int a, int b) { return rank(a) < rank(b); });
+        groups_.clear();  // the launches: runs of order_
         for (size_t k = 0; k < n; ++k) {
-            if (groups_.empty() || key(order_[k]) != key(order_[groups_.back().first]))
-                groups_.push_back({int(k), 0, 0, 1});
-            groups_.back().tiles += items[order_[k]].atom.n;  // points, until turned into tiles below
+            const int c = key(order_[k]);
+            const bool join = !groups_.empty() && (merge && ppl_of[c] == 1 ? groups_.back().mixed
+                                                                          : key(order_[groups_.back().first]) == c);
+            if (!join) groups_.push_back({int(k), int(k), 0, 0, ppl_of[c], merge && ppl_of[c] == 1});
+            Group& g = groups_.back();
+            g.end = int(k) + 1;
+            const Item& it = items[order_[k]];
+            g.bytes += it.atom.n * (it.lmax + 1) * (it.lmax + 1) * (it.atom.dtype == SH_F64 ? 8 : 4);
         }
-        for (Group& g : groups_) {
-            const Item& it = items[order_[g.first]];
-            const bool f64 = it.atom.dtype == SH_F64;
-            g.ppl = shk::group_ppl(it.atom.dtype, it.lmax, g.tiles);
-            g.bytes = g.tiles * (it.lmax + 1) * (it.lmax + 1) * (f64 ? 8 : 4);  // output bytes
-            g.tiles = 0;
-        }
-        // descriptors, then their first-tile indices (relative to their group), in one copy
+        // descriptors, then their first-tile indices (relative to their launch), in one copy
         int64_t* tile0 = reinterpret_cast<int64_t*>(s.host + n);
-        for (size_t gi = 0; gi < groups_.size(); ++gi) {
-            Group& g = groups_[gi];
-            const size_t end = gi + 1 < groups_.size() ? size_t(groups_[gi + 1].first) : n;
+        for (Group& g : groups_) {
             const int64_t tp = int64_t(shk::kServeBlock) * g.ppl;
-            for (size_t k = size_t(g.first); k < end; ++k) {
+            for (int k = g.first; k < g.end; ++k) {
                 const Item& it = items[order_[k]];
                 shk::ServeDesc& d = s.host[k];
                 memset(&d, 0, sizeof(d));
@@ -268,17 +340,14 @@ public:
             }
             if (g.tiles > max_tiles()) return SH_EINVAL;
         }
-        // groups of at most kInlineItems requests take their descriptors as arguments
-        auto items_of = [&](size_t gi) {
-            return (gi + 1 < groups_.size() ? groups_[gi + 1].first : int(n)) - groups_[gi].first;
-        };
+        // launches of at most kInlineItems requests take their descriptors as arguments
         bool copy = false;
-        for (size_t gi = 0; gi < groups_.size(); ++gi) copy = copy || items_of(gi) > shk::kInlineItems;
+        for (const Group& g : groups_) copy = copy || g.end - g.first > shk::kInlineItems;
         hipError_t e = copy ? hipMemcpyAsync(s.dev, s.host, (sizeof(shk::ServeDesc) + sizeof(int64_t)) * n,
                                              hipMemcpyHostToDevice, s.stream)
                             : hipSuccess;
         const int64_t* dev_tile0 = reinterpret_cast<const int64_t*>(s.dev + n);
-        // smallest output first, each group's completion recorded, so the requests of
+        // smallest output first, each launch's completion recorded, so the requests of
         // small groups complete without waiting for the large ones of the batch
         launch_order_.resize(groups_.size());
         for (size_t gi = 0; gi < groups_.size(); ++gi) launch_order_[gi] = int(gi);
@@ -288,10 +357,8 @@ public:
         s.group_end.clear();
         s.next = 0;
         for (size_t q = 0; q < launch_order_.size() && e == hipSuccess; ++q) {
-            const size_t gi = size_t(launch_order_[q]);
-            const Group& g = groups_[gi];
-            const int b = g.first;
-            const int m = items_of(gi);
+            const Group& g = groups_[size_t(launch_order_[q])];
+            const int b = g.first, m = g.end - g.first;
             const shk::ServeDesc& d = s.host[b];
             shk::ServeInline in;
             memset(&in, 0, sizeof(in));
@@ -299,8 +366,9 @@ public:
             if (inl) memcpy(in.d, s.host + b, sizeof(shk::ServeDesc) * m);
             const shk::ServeDesc* descs = inl ? nullptr : s.dev + b;
             const int64_t* t0 = inl ? nullptr : dev_tile0 + b;
-            e = d.dtype == SH_F64 ? shk::launch_group<double>(d.lmax, g.ppl, g.tiles, in, descs, t0, m, s.stream)
-                                  : shk::launch_group<float>(d.lmax, g.ppl, g.tiles, in, descs, t0, m, s.stream);
+            if (g.mixed) e = shk::launch_mixed(g.tiles, in, descs, t0, m, s.stream);
+            else if (d.dtype == SH_F64) e = shk::launch_group<double>(d.lmax, g.ppl, g.tiles, in, descs, t0, m, s.stream);
+            else e = shk::launch_group<float>(d.lmax, g.ppl, g.tiles, in, descs, t0, m, s.stream);
             if (e == hipSuccess) e = hipEventRecord(s.group_done[q], s.stream);
             for (int k = b; k < b + m; ++k) s.group_items.push_back(order_[k]);
             s.group_end.push_back(int(s.group_items.size()));
@@ -371,6 +439,7 @@ private:
         const int64_t* tile0 = reinterpret_cast<const int64_t*>(s.dev + 1);
         shk::ServeInline in;
         memset(&in, 0, sizeof(in));
+        if (e == hipSuccess) e = shk::launch_mixed(1, in, s.dev, tile0, 1, s.stream);
         for (int lmax = 0; lmax <= SH_LMAX && e == hipSuccess; ++lmax) {
             for (const int ppl : {1, shk::group_ppl(SH_F64, lmax, shk::kServeVecPoints)})
                 if (e == hipSuccess) e = shk::launch_group<double>(lmax, ppl, 1, in, s.dev, tile0, 1, s.stream);
@@ -381,14 +450,16 @@ private:
         return e != hipSuccess ? e : w;
     }
 
+    // one launch of a batch: one (dtype, lmax) group, or every one-point group (mixed)
     struct Group {
-        int first;      // first item (in order_)
-        int64_t tiles;  // tiles of the group's launch
-        int64_t bytes;  // output bytes
-        int ppl;        // points per lane
+        int first, end;  // its items: order_[first .. end)
+        int64_t tiles;   // tiles of the launch
+        int64_t bytes;   // output bytes
+        int ppl;         // points per lane
+        bool mixed;      // the mixed kernel
     };
-    std::vector<int> launch_order_;  // launch() scratch: groups, smallest output first
-    std::vector<Group> groups_;  // launch() scratch
+    std::vector<int> launch_order_;  // launch() scratch: launches, smallest output first
+    std::vector<Group> groups_;      // launch() scratch
 };
 
 }  // namespace

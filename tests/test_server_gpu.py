@@ -337,6 +337,53 @@ def test_descriptors_as_arguments_and_copied_in_one_batch(dev):
     radial.close()
 
 
+def test_one_point_groups_in_one_launch(dev):
+    """Small requests of different (dtype, lmax) in one batch run in one launch of
+    the mixed kernel: three requests (descriptors as kernel arguments), then seven
+    across five groups (descriptors copied), each batch formed behind a large
+    request that holds the only stream slot.  Each result equals sh_projectors of
+    its atom alone bit for bit."""
+    rng = np.random.default_rng(17)
+    batches = [[(1000, "f64", 2), (2000, "f32", 7), (3001, "f64", 9)],
+               [(513, "f32", 0), (700, "f64", 4), (701, "f64", 4), (1500, "f32", 9), (64, "f64", 1),
+                (65, "f64", 1), (9999, "f32", 5)]]
+    cases = [c for b in batches for c in b]
+    tabs = np.stack([workloads.radial_table(rng, 9, 2000, 3.0) for _ in range(len(cases) + 1)])
+    radial = sh.Radial(tabs, 3.0)
+    srv = Server(24 << 30, n_slots=1)
+    atoms, dev_pts, centers = [], [], []
+    for k, (n, dt, _) in enumerate(cases):
+        c = rng.uniform(0.0, 10.0, size=3).astype(np.float32 if dt == "f32" else np.float64).astype(np.float64)
+        t = torch.from_numpy(c + rng.uniform(-1.7, 1.7, size=(n, 3))).to(
+            dev, torch.float64 if dt == "f64" else torch.float32).contiguous()
+        dev_pts.append(t)
+        centers.append(c)
+        atoms.append(srv.add_atom(t, c, radial, table=k))
+    cb = np.array([5.0, 5.0, 5.0])
+    blk = torch.from_numpy(cb + rng.uniform(-1.7, 1.7, size=(1 << 24, 3))).to(dev).contiguous()
+    ablk = srv.add_atom(blk, cb, radial, table=len(cases))
+    k0 = 0
+    for bi, batch in enumerate(batches):
+        _say("case: one-point groups in one launch, batch", bi, "of", len(batch), "requests")
+        b0 = srv.stats()["batches"]
+        tb = srv.submit(ablk, 9)
+        while srv.poll(tb) < RUNNING:
+            pass
+        tickets = [srv.submit(atoms[k0 + k], lmax) for k, (_, _, lmax) in enumerate(batch)]
+        for t in [tb] + tickets:
+            assert srv.wait(t, 60) == DONE
+        assert srv.stats()["batches"] - b0 == 2
+        for k, (t, (n, dt, lmax)) in enumerate(zip(tickets, batch)):
+            a = k0 + k
+            got = srv.result(t, lmax, n, torch.float64 if dt == "f64" else torch.float32)
+            assert torch.equal(got.reshape(-1), _alone(dev, lmax, centers[a], dev_pts[a], radial, a)), (bi, k)
+            srv.release(t)
+        srv.release(tb)
+        k0 += len(batch)
+    srv.close()
+    radial.close()
+
+
 def test_release_waits_for_the_callers_stream(dev):
     """The server may give a released output's memory to the next request at once,
     on its own stream; the Python binding's release() first waits for the work
