@@ -533,8 +533,8 @@ def counter_summary(paths, chunk: int = 0, kernels: str = "") -> None:
 
 def serving_trace_summary(path: str, gap_ns: int = 2_000_000) -> None:
     """Per-pass view of a rocprofv3 kernel trace (`*_kernel_trace.csv`) of the
-    serving section: its serve_kernel dispatches (warm-up launches of one tile
-    left out) split where no serving kernel runs for more than gap_ns; for each
+    serving section: its serve_kernel and serve_mixed_kernel dispatches (warm-up
+    launches of one tile left out) split where no serving kernel runs for more than gap_ns; for each
     pass the dispatch count, span, the share of the span with 0, 1, 2 or 3 serving
     kernels running, their summed duration, and the kernels with the most time."""
     import collections
@@ -547,7 +547,7 @@ def serving_trace_summary(path: str, gap_ns: int = 2_000_000) -> None:
         return int(r.get("Grid_Size") or r.get("Grid_Size_X") or 0)
 
     ds = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"]) for r in rows
-                if "serve_kernel" in r["Kernel_Name"] and grid(r) > 256)
+                if ("serve_kernel" in r["Kernel_Name"] or "serve_mixed_kernel" in r["Kernel_Name"]) and grid(r) > 256)
     passes, cur, end = [], [], 0
     for d in ds:
         if cur and d[0] - end > gap_ns:
@@ -568,11 +568,11 @@ def serving_trace_summary(path: str, gap_ns: int = 2_000_000) -> None:
             c, last = c + dlt, t
         per = collections.defaultdict(lambda: [0, 0.0])
         for s, e, name in p:
-            m = re.search(r"serve_kernel<[^>]*>", name)
+            m = re.search(r"serve_kernel<[^>]*>|serve_mixed_kernel", name)
             per[m.group(0) if m else name][0] += 1
             per[m.group(0) if m else name][1] += (e - s) / 1e6
         busy = sum(v[1] for v in per.values())
-        one = sum(v[1] for kk, v in per.items() if kk.endswith(", 1>"))
+        one = sum(v[1] for kk, v in per.items() if kk.endswith(", 1>") or kk == "serve_mixed_kernel")
         print(f"pass {k}: {len(p)} dispatches over {span / 1e6:.2f} ms; share of the span with "
               + ", ".join(f"{n} running {at[n] / span:.3f}" for n in sorted(at))
               + f"; kernel time {busy:.1f} ms ({one:.1f} ms in one-point-per-lane launches)")

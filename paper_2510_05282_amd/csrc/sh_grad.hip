@@ -152,7 +152,11 @@ static hipError_t launch_jac_one(int64_t n, const double* xyz, double* out, doub
 template <int LMAX>
 static hipError_t launch_jac_l(int64_t n, const double* xyz, double* out, double* jac, int64_t ld, hipStream_t s)
 {
-    const bool vec_ok = ld % 2 == 0 && reinterpret_cast<uintptr_t>(out) % 16 == 0 &&
+    // several points per lane from 2^18 points on (a smaller launch leaves CUs idle
+    // and lasts one workgroup's chain of work, which the wider lanes lengthen: lmax
+    // 6, 4k / 16k / 64k / 100k points, 7.4 / 9.2 / 16.4 / 24.4 us against 8.6 /
+    // 10.6 / 16.8 / 24.9 with two points per lane)
+    const bool vec_ok = n >= (int64_t(1) << 18) && ld % 2 == 0 && reinterpret_cast<uintptr_t>(out) % 16 == 0 &&
                         reinterpret_cast<uintptr_t>(jac) % 16 == 0;
     for (int64_t c0 = 0; c0 < n; c0 += kGradChunk) {
         const int64_t nc = n - c0 < kGradChunk ? n - c0 : kGradChunk;

@@ -35,6 +35,17 @@ static_assert(shc::kRecLmax == SH_LMAX_REC, "recurrence tables and the public li
 
 constexpr int kRecBlock = 256;
 constexpr int64_t kRecChunk = int64_t(1) << 28;
+// Calls of at least this many points take several points per lane; smaller
+// launches leave CUs idle and last one workgroup's chain of work, which the wider
+// lanes lengthen, so they run one point per lane.  Kernel trace, 4k / 16k / 64k /
+// 100k points, one point per lane against the wide lanes: real harmonics at lmax
+// 16 FP64 25.1 / 27.3 / 33.1 / 48.5 us against 30.3 / 32.3 / 37.2 / 44.5, FP32
+// 24.6 / 29.2 / 35.3 / 35.7 against 36.0 / 40.2 / 45.4 / 45.6; the backward pass at
+// lmax 14 FP64 38.2 / 74.1 / 76.9 / 83.9 against 44.2 / 83.2 / 85.9 / 88.0; equal
+// at 2^18 points.  The FP64 forward switches between 64k and 100k points.
+// (real harmonics; the complex and spinor forms and the backward pass switch at 2^18)
+template <typename TIO> constexpr int64_t kRecVecPoints = sizeof(TIO) == 8 ? int64_t(3) << 15 : int64_t(1) << 18;
+constexpr int64_t kRecVecPointsCplxGrad = int64_t(1) << 18;
 constexpr size_t kRecCapLds = 54 * 1024;
 
 // TIO = double: 2 points per lane (PPL = 2); float: 4 (PPL = 4); both store 16
@@ -67,7 +78,7 @@ template <typename TIO>
 hipError_t launch_rec(int lmax, int64_t n, const TIO* xyz, TIO* out, int64_t ld, hipStream_t s)
 {
     constexpr int kVec = 16 / sizeof(TIO);
-    const bool vec_ok = ld % kVec == 0 && reinterpret_cast<uintptr_t>(out) % 16 == 0;
+    const bool vec_ok = n >= kRecVecPoints<TIO> && ld % kVec == 0 && reinterpret_cast<uintptr_t>(out) % 16 == 0;
     for (int64_t c0 = 0; c0 < n; c0 += kRecChunk) {
         const int64_t nc = n - c0 < kRecChunk ? n - c0 : kRecChunk;
         const int64_t nmain = vec_ok ? nc - nc % kVec : 0;
@@ -146,7 +157,8 @@ template <typename TIO>
 hipError_t launch_grad_rec(int lmax, int64_t n, const TIO* xyz, const TIO* G, int64_t ldg, TIO* gxyz, hipStream_t s)
 {
     constexpr int kVec = 2;
-    const bool vec_ok = ldg % kVec == 0 && reinterpret_cast<uintptr_t>(G) % (kVec * sizeof(TIO)) == 0;
+    const bool vec_ok =
+        n >= kRecVecPointsCplxGrad && ldg % kVec == 0 && reinterpret_cast<uintptr_t>(G) % (kVec * sizeof(TIO)) == 0;
     for (int64_t c0 = 0; c0 < n; c0 += kRecChunk) {  // kRecChunk is a multiple of kVec
         const int64_t nc = n - c0 < kRecChunk ? n - c0 : kRecChunk;
         const int64_t nmain = vec_ok ? nc - nc % kVec : 0;
@@ -206,7 +218,7 @@ static hipError_t launch_rec_cplx(int lmax, int64_t n, int input, const TIO* in0
     constexpr int kVec = sizeof(TIO) == 4 ? 2 : 1;
     const In mode = In(input);
     const int64_t stride = mode == In::kAngles ? 1 : 3;
-    const bool vec_ok = ld % kVec == 0 && reinterpret_cast<uintptr_t>(out) % 16 == 0;
+    const bool vec_ok = n >= kRecVecPointsCplxGrad && ld % kVec == 0 && reinterpret_cast<uintptr_t>(out) % 16 == 0;
     for (int64_t c0 = 0; c0 < n; c0 += kRecChunk) {
         const int64_t nc = n - c0 < kRecChunk ? n - c0 : kRecChunk;
         const int64_t nmain = vec_ok ? nc - nc % kVec : 0;

@@ -59,8 +59,11 @@ def test_real_harmonics_vector_and_single_lanes(dev, dtype):
 
 def test_other_kernels_vector_and_single_lanes(dev):
     """The same for the kernels with two FP64 / four FP32 points per lane and a
-    one-point tail: complex (FP32), recurrence, and the backward passes."""
-    n = 20001
+    one-point tail (n = 2^18 + 1; the vector launches start at 2^18 points, the
+    FP64 recurrence at 3 x 2^15): complex (FP32), recurrence, the fused values and
+    Jacobian, and the backward passes; and 2^18 - 1 points (one point per lane
+    except the FP64 recurrence)."""
+    n = (1 << 18) + 1
     for dtype in (torch.float64, torch.float32):
         x = _pts(n, 2, dtype, dev)
         xs = x[1:].contiguous()
@@ -68,9 +71,13 @@ def test_other_kernels_vector_and_single_lanes(dev):
         cases = [("rec lmax 12", lambda a: (sh.sh_eval_rec_f32 if f32 else sh.sh_eval_rec)(12, a))]
         if f32:
             cases.append(("complex lmax 9", lambda a: sh.sh_eval_complex_f32(9, a)))
+        else:
+            cases.append(("jacobian lmax 6", lambda a: torch.cat([t.reshape(-1, t.shape[-1]) for t in sh.sh_eval_jac(6, a)])))
         for name, f in cases:
             _say("case: lane identity,", name, dtype)
-            assert torch.equal(f(x)[..., 1:], f(xs)), name
+            full = f(x)
+            assert torch.equal(full[..., 1:], f(xs)), name
+            assert torch.equal(full[..., 2:], f(x[2:].contiguous())), name
         for lmax, fn in ((6, sh.sh_eval_grad_f32 if f32 else sh.sh_eval_grad),
                          (14, sh.sh_eval_grad_rec_f32 if f32 else sh.sh_eval_grad_rec)):
             F = (lmax + 1) ** 2
@@ -78,7 +85,9 @@ def test_other_kernels_vector_and_single_lanes(dev):
             gen.manual_seed(lmax)
             G = torch.randn((F, n), generator=gen, dtype=dtype, device=dev)
             _say("case: lane identity, backward lmax", lmax, dtype)
-            assert torch.equal(fn(lmax, x, G)[1:], fn(lmax, xs, G[:, 1:].contiguous()))
+            full = fn(lmax, x, G)
+            assert torch.equal(full[1:], fn(lmax, xs, G[:, 1:].contiguous()))
+            assert torch.equal(full[2:], fn(lmax, x[2:].contiguous(), G[:, 2:].contiguous()))
 
 
 @pytest.mark.parametrize("lmax", [0, 2, 3, 5])
