@@ -261,14 +261,14 @@ int sh_projectors_noalloc(int lmax, int dtype, int n_atoms, const void *centers,
  * requests in arrival order while their output fits in an HBM budget (carved
  * from one device allocation made at creation), packs all admitted requests into
  * one batch and launches it on a free stream slot (one kernel per (dtype, lmax)
- * group of the batch), so requests that arrive while others run are admitted as
- * memory and slots free up and their work overlaps on the device.  Results stay
- * on the device until released.  Within a batch the groups run smallest output
- * first and each request completes when its group does.  A request's latency is
- * measured from sh_server_submit to the host seeing its group complete.  Creation
- * also runs every serving kernel once on an empty request, so that no first
- * launch (which is slow) falls in the middle of serving.  Every function is
- * thread-safe.
+ * group of the batch; the small groups of a batch may share one), so requests
+ * that arrive while others run are admitted as memory and slots free up and their
+ * work overlaps on the device.  Results stay on the device until released.
+ * Within a batch the launches run smallest output first and each request
+ * completes when its launch does.  A request's latency is measured from
+ * sh_server_submit to the host seeing its launch complete.  Creation also runs
+ * every serving kernel once on an empty request, so that no first launch (which
+ * is slow) falls in the middle of serving.  Every function is thread-safe.
  */
 typedef struct sh_server *sh_server_t;
 

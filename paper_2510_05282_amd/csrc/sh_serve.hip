@@ -9,15 +9,17 @@
 // occupancy sized for that lmax, no per-point dispatch); the one-point groups share
 // one launch of the mixed kernel when there are two or more of them (a block runs
 // the code of its request's (dtype, lmax)), which saves the host a launch and an
-// event per extra group.  The launches go smallest output first, each followed by
-// an event, and progress() reports a launch's requests as soon as its event
-// completes.  A launch of at most kInlineItems requests takes their descriptors as
+// event per extra group.  The launches go smallest output first, each with its
+// group's event as the launch's own completion event (hipExtLaunchKernel: no
+// separate event record), and progress() reports a launch's requests as soon as
+// its event completes.  A launch of at most kInlineItems requests takes their descriptors as
 // kernel arguments; the descriptors of larger launches and their first-tile
 // indices travel host -> device in one copy per batch through a pinned staging
 // buffer per slot (the slot is reused only after its previous batch has completed,
 // so the staging buffer is never overwritten in flight), and a batch with no
 // larger launch makes no copy.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stdint.h>
 #include <string.h>
 
@@ -150,23 +152,24 @@ __global__ __launch_bounds__(kServeBlock) void serve_mixed_kernel(ServeInline in
 }
 
 static hipError_t launch_mixed(int64_t tiles, const ServeInline& in, const ServeDesc* descs, const int64_t* tile0,
-                               int n, hipStream_t s)
+                               int n, hipStream_t s, hipEvent_t done)
 {
     if (descs == nullptr && (n < 1 || n > kInlineItems)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(serve_mixed_kernel, dim3(unsigned(tiles)), dim3(kServeBlock), 0, s, in, descs, tile0, n);
+    hipExtLaunchKernelGGL(serve_mixed_kernel, dim3(unsigned(tiles)), dim3(kServeBlock), 0, s, nullptr, done, 0, in,
+                          descs, tile0, n);
     return hipGetLastError();
 }
 
 template <int LMAX, typename TIO>
 static void launch_group_l(int ppl, int64_t tiles, const ServeInline& in, const ServeDesc* descs,
-                           const int64_t* tile0, int n, hipStream_t s)
+                           const int64_t* tile0, int n, hipStream_t s, hipEvent_t done)
 {
     const dim3 grid = dim3(unsigned(tiles)), block = dim3(kServeBlock);
     if (ppl == 1)
-        hipLaunchKernelGGL((serve_kernel<LMAX, TIO, 1>), grid, block, 0, s, in, descs, tile0, n);
+        hipExtLaunchKernelGGL((serve_kernel<LMAX, TIO, 1>), grid, block, 0, s, nullptr, done, 0, in, descs, tile0, n);
     else
-        hipLaunchKernelGGL((serve_kernel<LMAX, TIO, kProjPpl<TIO, LMAX>>), grid, block, (kProjCapLds<TIO, LMAX>), s,
-                           in, descs, tile0, n);
+        hipExtLaunchKernelGGL((serve_kernel<LMAX, TIO, kProjPpl<TIO, LMAX>>), grid, block,
+                              uint32_t(kProjCapLds<TIO, LMAX>), s, nullptr, done, 0, in, descs, tile0, n);
 }
 
 // Groups of at least this many points take several points per lane.  Lower than
@@ -196,20 +199,20 @@ static int group_ppl(int dtype, int lmax, int64_t n)
 // of `in`, else n descriptors at descs and their first tiles at tile0 (device)
 template <typename TIO>
 static hipError_t launch_group(int lmax, int ppl, int64_t tiles, const ServeInline& in, const ServeDesc* descs,
-                               const int64_t* tile0, int n, hipStream_t s)
+                               const int64_t* tile0, int n, hipStream_t s, hipEvent_t done)
 {
     if (descs == nullptr && (n < 1 || n > kInlineItems)) return hipErrorInvalidValue;
     switch (lmax) {
-    case 0: launch_group_l<0, TIO>(ppl, tiles, in, descs, tile0, n, s); break;
-    case 1: launch_group_l<1, TIO>(ppl, tiles, in, descs, tile0, n, s); break;
-    case 2: launch_group_l<2, TIO>(ppl, tiles, in, descs, tile0, n, s); break;
-    case 3: launch_group_l<3, TIO>(ppl, tiles, in, descs, tile0, n, s); break;
-    case 4: launch_group_l<4, TIO>(ppl, tiles, in, descs, tile0, n, s); break;
-    case 5: launch_group_l<5, TIO>(ppl, tiles, in, descs, tile0, n, s); break;
-    case 6: launch_group_l<6, TIO>(ppl, tiles, in, descs, tile0, n, s); break;
-    case 7: launch_group_l<7, TIO>(ppl, tiles, in, descs, tile0, n, s); break;
-    case 8: launch_group_l<8, TIO>(ppl, tiles, in, descs, tile0, n, s); break;
-    case 9: launch_group_l<9, TIO>(ppl, tiles, in, descs, tile0, n, s); break;
+    case 0: launch_group_l<0, TIO>(ppl, tiles, in, descs, tile0, n, s, done); break;
+    case 1: launch_group_l<1, TIO>(ppl, tiles, in, descs, tile0, n, s, done); break;
+    case 2: launch_group_l<2, TIO>(ppl, tiles, in, descs, tile0, n, s, done); break;
+    case 3: launch_group_l<3, TIO>(ppl, tiles, in, descs, tile0, n, s, done); break;
+    case 4: launch_group_l<4, TIO>(ppl, tiles, in, descs, tile0, n, s, done); break;
+    case 5: launch_group_l<5, TIO>(ppl, tiles, in, descs, tile0, n, s, done); break;
+    case 6: launch_group_l<6, TIO>(ppl, tiles, in, descs, tile0, n, s, done); break;
+    case 7: launch_group_l<7, TIO>(ppl, tiles, in, descs, tile0, n, s, done); break;
+    case 8: launch_group_l<8, TIO>(ppl, tiles, in, descs, tile0, n, s, done); break;
+    case 9: launch_group_l<9, TIO>(ppl, tiles, in, descs, tile0, n, s, done); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -366,10 +369,10 @@ public:
             if (inl) memcpy(in.d, s.host + b, sizeof(shk::ServeDesc) * m);
             const shk::ServeDesc* descs = inl ? nullptr : s.dev + b;
             const int64_t* t0 = inl ? nullptr : dev_tile0 + b;
-            if (g.mixed) e = shk::launch_mixed(g.tiles, in, descs, t0, m, s.stream);
-            else if (d.dtype == SH_F64) e = shk::launch_group<double>(d.lmax, g.ppl, g.tiles, in, descs, t0, m, s.stream);
-            else e = shk::launch_group<float>(d.lmax, g.ppl, g.tiles, in, descs, t0, m, s.stream);
-            if (e == hipSuccess) e = hipEventRecord(s.group_done[q], s.stream);
+            hipEvent_t ev = s.group_done[q];
+            if (g.mixed) e = shk::launch_mixed(g.tiles, in, descs, t0, m, s.stream, ev);
+            else if (d.dtype == SH_F64) e = shk::launch_group<double>(d.lmax, g.ppl, g.tiles, in, descs, t0, m, s.stream, ev);
+            else e = shk::launch_group<float>(d.lmax, g.ppl, g.tiles, in, descs, t0, m, s.stream, ev);
             for (int k = b; k < b + m; ++k) s.group_items.push_back(order_[k]);
             s.group_end.push_back(int(s.group_items.size()));
         }
@@ -382,8 +385,8 @@ public:
         return SH_OK;
     }
 
-    // The batch's last launch is its last group's, followed by that group's event:
-    // the batch is complete when that event is.
+    // The batch's last launch is its last group's, which completes that group's
+    // event: the batch is complete when that event is.
     int query(int slot) override
     {
         const Slot& s = slots_[slot];
@@ -439,12 +442,12 @@ private:
         const int64_t* tile0 = reinterpret_cast<const int64_t*>(s.dev + 1);
         shk::ServeInline in;
         memset(&in, 0, sizeof(in));
-        if (e == hipSuccess) e = shk::launch_mixed(1, in, s.dev, tile0, 1, s.stream);
+        if (e == hipSuccess) e = shk::launch_mixed(1, in, s.dev, tile0, 1, s.stream, nullptr);
         for (int lmax = 0; lmax <= SH_LMAX && e == hipSuccess; ++lmax) {
             for (const int ppl : {1, shk::group_ppl(SH_F64, lmax, shk::kServeVecPoints)})
-                if (e == hipSuccess) e = shk::launch_group<double>(lmax, ppl, 1, in, s.dev, tile0, 1, s.stream);
+                if (e == hipSuccess) e = shk::launch_group<double>(lmax, ppl, 1, in, s.dev, tile0, 1, s.stream, nullptr);
             for (const int ppl : {1, shk::group_ppl(SH_F32, lmax, shk::kServeVecPoints)})
-                if (e == hipSuccess) e = shk::launch_group<float>(lmax, ppl, 1, in, s.dev, tile0, 1, s.stream);
+                if (e == hipSuccess) e = shk::launch_group<float>(lmax, ppl, 1, in, s.dev, tile0, 1, s.stream, nullptr);
         }
         const hipError_t w = hipStreamSynchronize(s.stream);
         return e != hipSuccess ? e : w;
