@@ -410,7 +410,8 @@ def bench_projectors(sh, workloads, dev, steps):
     large = {"workload": "64 atoms x 150k points, balls of radius 3", "n_points": nl}
     for name, lmax, dt in (("lmax0_f64", 0, torch.float64), ("lmax1_f64", 1, torch.float64),
                            ("lmax3_f64", 3, torch.float64), ("lmax6_f64", 6, torch.float64),
-                           ("lmax9_f64", 9, torch.float64), ("lmax3_f32", 3, torch.float32),
+                           ("lmax9_f64", 9, torch.float64), ("lmax0_f32", 0, torch.float32),
+                           ("lmax1_f32", 1, torch.float32), ("lmax3_f32", 3, torch.float32),
                            ("lmax6_f32", 6, torch.float32), ("lmax9_f32", 9, torch.float32)):
         F, sz = (lmax + 1) ** 2, (8 if dt == torch.float64 else 4)
         pl, cl = pts.to(dt), cen.to(dt)

@@ -24,10 +24,31 @@ struct SplineGrid {
 // R_0 .. R_{NL-1} at r >= 0 from a table with ch >= NL channels: interval
 // i = floor(r/h) clamped to [0, n_r-2], t = r/h - i, A = 1 - t, B = t,
 //     S = A y_i + B y_{i+1} + ((A^3 - A) M_i + (B^3 - B) M_{i+1}) h^2/6;
-// 0 beyond r_max; a NaN r gives NaN.
+// 0 beyond r_max; a NaN r gives NaN.  Split in two steps: spline_knots loads
+// the pairs of knots i and i+1 (for any r: beyond r_max or NaN it reads interval 0,
+// which spline_from then ignores), spline_from evaluates the cubic from them.
+__host__ __device__ __forceinline__ int spline_interval(double r, const SplineGrid& g)
+{
+    const double q = r <= g.r_max ? r * g.inv_h : 0.0;
+    const int i = int(q);
+    return i > g.n_r - 2 ? g.n_r - 2 : i;
+}
+
+template <int NL, typename KN>
+__host__ __device__ __forceinline__ void spline_knots(const KN* __restrict__ tab, int ch, const SplineGrid& g,
+                                                      double r, KN (&a)[NL], KN (&b)[NL])
+{
+    const KN* k0 = tab + int64_t(spline_interval(r, g)) * ch;
+    static_for<0, NL>([&](auto lc) {
+        constexpr int L = decltype(lc)::value;
+        a[L] = k0[L];
+        b[L] = k0[ch + L];
+    });
+}
+
 template <int NL, typename TIO>
-__host__ __device__ __forceinline__ void spline_eval(const double2* __restrict__ tab, int ch, const SplineGrid& g,
-                                                     double r, TIO (&R)[NL])
+__host__ __device__ __forceinline__ void spline_from(const double2 (&a)[NL], const double2 (&b)[NL],
+                                                     const SplineGrid& g, double r, TIO (&R)[NL])
 {
     if (!(r <= g.r_max)) {
         const double v = r != r ? r : 0.0;
@@ -35,26 +56,21 @@ __host__ __device__ __forceinline__ void spline_eval(const double2* __restrict__
         return;
     }
     const double q = r * g.inv_h;
-    int i = int(q);
-    i = i > g.n_r - 2 ? g.n_r - 2 : i;
-    const double t = q - double(i);
+    const double t = q - double(spline_interval(r, g));
     const double A = 1.0 - t, B = t;
-    const double2* k0 = tab + int64_t(i) * ch;
-    const double2* k1 = k0 + ch;
     static_for<0, NL>([&](auto lc) {
         constexpr int L = decltype(lc)::value;
-        const double2 a = k0[L], b = k1[L];
-        R[L] = TIO(A * a.x + B * b.x + ((A * A * A - A) * a.y + (B * B * B - B) * b.y) * g.h2_over_6);
+        R[L] = TIO(A * a[L].x + B * b[L].x + ((A * A * A - A) * a[L].y + (B * B * B - B) * b[L].y) * g.h2_over_6);
     });
 }
 
-// The same from a table of float pairs, for the FP32 kernels: the interval i and
-// t = r/h - i in FP64 (near r_max, r/h is ~n_r, and float would leave t only a few
-// bits), the cubic in FP32.  Table values rounded to float and the FP32 cubic put
-// at most a few 1e-7 (of max|R|) into R, well inside the FP32 tolerance.
+// The same from float pairs, for the FP32 kernels: the interval i and t = r/h - i
+// in FP64 (near r_max, r/h is ~n_r, and float would leave t only a few bits), the
+// cubic in FP32.  Table values rounded to float and the FP32 cubic put at most a
+// few 1e-7 (of max|R|) into R, well inside the FP32 tolerance.
 template <int NL, typename TIO>
-__host__ __device__ __forceinline__ void spline_eval(const float2* __restrict__ tab, int ch, const SplineGrid& g,
-                                                     double r, TIO (&R)[NL])
+__host__ __device__ __forceinline__ void spline_from(const float2 (&a)[NL], const float2 (&b)[NL],
+                                                     const SplineGrid& g, double r, TIO (&R)[NL])
 {
     static_assert(sizeof(TIO) == 4, "float tables serve the FP32 kernels");
     if (!(r <= g.r_max)) {
@@ -63,17 +79,22 @@ __host__ __device__ __forceinline__ void spline_eval(const float2* __restrict__ 
         return;
     }
     const double q = r * g.inv_h;
-    int i = int(q);
-    i = i > g.n_r - 2 ? g.n_r - 2 : i;
-    const float t = float(q - double(i));
+    const float t = float(q - double(spline_interval(r, g)));
     const float A = 1.0f - t, B = t, h26 = float(g.h2_over_6);
-    const float2* k0 = tab + int64_t(i) * ch;
-    const float2* k1 = k0 + ch;
     static_for<0, NL>([&](auto lc) {
         constexpr int L = decltype(lc)::value;
-        const float2 a = k0[L], b = k1[L];
-        R[L] = A * a.x + B * b.x + ((A * A * A - A) * a.y + (B * B * B - B) * b.y) * h26;
+        R[L] = A * a[L].x + B * b[L].x + ((A * A * A - A) * a[L].y + (B * B * B - B) * b[L].y) * h26;
     });
+}
+
+// Both steps for one point, with the loads skipped beyond r_max.
+template <int NL, typename TIO, typename KN>
+__host__ __device__ __forceinline__ void spline_eval(const KN* __restrict__ tab, int ch, const SplineGrid& g,
+                                                     double r, TIO (&R)[NL])
+{
+    KN a[NL], b[NL];
+    if (r <= g.r_max) spline_knots<NL>(tab, ch, g, r, a, b);
+    spline_from<NL, TIO>(a, b, g, r, R);
 }
 
 // Natural cubic spline on a uniform grid for one channel.  With knot spacing h
@@ -224,6 +245,16 @@ constexpr int64_t kProjVecPoints = int64_t(1) << 20;
 // without it (the FP64 lmax 0 launch with two points per lane: 45% against 34%).
 template <typename TIO, int LMAX>
 constexpr size_t kProjCapLds = (sizeof(TIO) == 4 ? LMAX <= 1 : LMAX == 0) ? 0 : 54 * 1024;
+
+// Whether builds with several points per lane over at most 64 atoms run
+// proj_vec_kernel (atoms held in lanes, every knot load of a lane issued before the
+// first spline) instead of proj_kernel (a wave-wide search for the atom, then each
+// point's knots loaded and used in turn).  Measured on 64 x 150k-point builds, two
+// runs each, fractions of 8 TB/s: FP32 lmax 0 / 1 / 2 / 3 / 4 47 / 44-50 / 44 / 53 /
+// 58% -> 53 / 52-56 / 45 / 56-57 / 60%, FP64 lmax 3 57 -> 58-59%; FP32 lmax 5-9 within
+// +-0.5%, FP64 lmax 0-2 and 4-9 0-2% slower.
+template <typename TIO, int LMAX>
+constexpr bool kProjVecSmall = sizeof(TIO) == 4 ? LMAX <= 4 : LMAX == 3;
 
 // Lane width of a launch of n points.
 template <typename TIO, int LMAX> constexpr int proj_ppl(int64_t n) { return n >= kProjVecPoints ? kProjPpl<TIO, LMAX> : 1; }

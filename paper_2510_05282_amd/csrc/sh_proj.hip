@@ -17,7 +17,8 @@
 // (their tables then stay in that XCD's L2); the atom of a wave found by one
 // wave-wide search; plain stores; one point per lane, or, for builds of at least
 // kProjVecPoints points, kProjPpl adjacent points per lane evaluated together, with
-// at most 2 resident workgroups per CU (kProjCapLds).
+// at most 2 resident workgroups per CU (kProjCapLds); those builds run
+// proj_vec_kernel where kProjVecSmall is set (up to 64 atoms).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -55,9 +56,10 @@ __global__ void spline_setup_kernel(const double* __restrict__ y, double2* __res
 // point loads and the arithmetic.  Otherwise, and for lanes past atom aw + 1, the
 // wave's atom comes from a wave-wide search and a lane's from a binary search, and
 // the atom's data is loaded after it.  Measured on the 64-atom lmax 3 build (one
-// point per lane): 29.6-29.8 us -> 27.6-28.0 us.  The launches with several points
-// per lane keep the search: there the extra registers cost as much as the shorter
-// chain saves (-6% to +5% across lmax and dtype on 64 x 150k-point builds).
+// point per lane): 29.6-29.8 us -> 27.6-28.0 us.  In this kernel the launches with
+// several points per lane keep the search: there the preload alone cost as much as
+// the shorter chain saved (-6% to +5% across lmax and dtype on 64 x 150k-point
+// builds); proj_vec_kernel combines it with loading every knot of a lane at once.
 struct AtomRef {
     int64_t o0, o1;  // its point range
     double c[3];
@@ -155,9 +157,118 @@ __global__ __launch_bounds__(256) void proj_kernel(const TIO* __restrict__ cente
     }
 }
 
+// The launches with several points per lane over at most 64 atoms, for the
+// (dtype, lmax) where kProjVecSmall is set: lane k loads atom k's offsets, centre
+// and table with the points (as the one-point SMALL path does), a ballot gives the
+// wave's atom and the next, and a lane then issues the knot loads of all its
+// points before it evaluates any spline (spline_knots, then spline_from), so the
+// chain per lane is the point loads, one wave of knot loads and the stores.  Each
+// lane's points lie in one of those two atoms unless the wave crosses more than
+// one atom boundary; such lanes, and lanes that straddle a boundary, take their
+// points one by one.  The same arithmetic as proj_kernel, so the same bits.
+template <int LMAX, typename TIO, int PPL>
+__global__ __launch_bounds__(256) void proj_vec_kernel(const TIO* __restrict__ centers,
+                                                       const int64_t* __restrict__ offsets, int n_atoms,
+                                                       const TIO* __restrict__ points, int64_t n_points,
+                                                       const knot_t<TIO>* __restrict__ table, int tab_ch,
+                                                       int n_tables, const int32_t* __restrict__ table_of_atom,
+                                                       SplineGrid g, TIO* __restrict__ out, int64_t j0)
+{
+    using V = typename vec_of<TIO, PPL>::type;
+    constexpr int F = nfun(LMAX);
+    const int64_t w0 = j0 + (int64_t(xcd_tile(blockIdx.x, gridDim.x)) * 256 + (threadIdx.x & ~63u)) * PPL;
+    if (w0 >= n_points) return;
+    const int wl = threadIdx.x & 63;  // lane in the wave
+    auto load_atom = [&](int a) {
+        AtomRef r;
+        r.o0 = offsets[a];
+        r.o1 = offsets[a + 1];
+        r.c[0] = double(centers[3 * a]);
+        r.c[1] = double(centers[3 * a + 1]);
+        r.c[2] = double(centers[3 * a + 2]);
+        const int t = table_of_atom ? table_of_atom[a] : a;
+        r.t = t < 0 ? 0 : (t >= n_tables ? n_tables - 1 : t);
+        return r;
+    };
+    AtomRef mine{};
+    if (wl < n_atoms) mine = load_atom(wl);
+    const int64_t j = w0 + wl * PPL;
+    double px[PPL], py[PPL], pz[PPL];
+#pragma unroll
+    for (int q = 0; q < PPL; ++q) {
+        const TIO* p = points + 3 * (j + q < n_points ? j + q : w0);
+        px[q] = double(p[0]);
+        py[q] = double(p[1]);
+        pz[q] = double(p[2]);
+    }
+    auto atom_at = [&](int a) {
+        return AtomRef{lane_value(mine.o0, a), lane_value(mine.o1, a),
+                       {lane_value(mine.c[0], a), lane_value(mine.c[1], a), lane_value(mine.c[2], a)},
+                       lane_value(mine.t, a)};
+    };
+    const int aw = __popcll(__ballot(wl < n_atoms && mine.o0 <= w0)) - 1;
+    AtomRef A0, A1;  // atoms aw and aw + 1 (o0 = o1 = -1 if there is none)
+    A0.o0 = A0.o1 = A1.o0 = A1.o1 = -1;
+    if (aw >= 0) A0 = atom_at(aw);
+    if (aw + 1 < n_atoms) A1 = atom_at(aw + 1);
+    if (j >= n_points) return;
+    const bool in0 = A0.o0 >= 0 && A0.o0 <= j && j + PPL <= A0.o1 && A0.o1 <= n_points;
+    const bool in1 = A1.o0 >= 0 && A1.o0 <= j && j + PPL <= A1.o1 && A1.o1 <= n_points;
+    if (!in0 && !in1) {
+#pragma unroll
+        for (int q = 0; q < PPL; ++q) {
+            const int64_t jq = j + q;
+            if (jq >= n_points) break;
+            const AtomRef B = load_atom(lane_search(offsets, n_atoms, jq));
+            if (!(B.o0 >= 0 && B.o0 <= jq && jq < B.o1 && B.o1 <= n_points)) continue;
+            proj_point<LMAX, TIO>(px[q], py[q], pz[q], B.c, table + int64_t(B.t) * g.n_r * tab_ch, tab_ch, g,
+                                  out + F * B.o0 + (jq - B.o0), B.o1 - B.o0);
+        }
+        return;
+    }
+    const AtomRef& A = in0 ? A0 : A1;
+    const knot_t<TIO>* tab = table + int64_t(A.t) * g.n_r * tab_ch;
+    knot_t<TIO> ka[PPL][LMAX + 1], kb[PPL][LMAX + 1];
+    double r[PPL];
+    V x, y, z, k;
+#pragma unroll
+    for (int q = 0; q < PPL; ++q) {
+        const double dx = px[q] - A.c[0], dy = py[q] - A.c[1], dz = pz[q] - A.c[2];
+        double xb, yb, zb, keep;
+        normalize(dx, dy, dz, xb, yb, zb, keep);
+        r[q] = sqrt(__builtin_fma(dx, dx, __builtin_fma(dy, dy, dz * dz)));
+        spline_knots<LMAX + 1>(tab, tab_ch, g, r[q], ka[q], kb[q]);
+        lane<V, PPL>(x, q) = TIO(xb);
+        lane<V, PPL>(y, q) = TIO(yb);
+        lane<V, PPL>(z, q) = TIO(zb);
+        lane<V, PPL>(k, q) = TIO(keep);
+    }
+    TIO R[PPL][LMAX + 1];
+#pragma unroll
+    for (int q = 0; q < PPL; ++q) spline_from<LMAX + 1, TIO>(ka[q], kb[q], g, r[q], R[q]);
+    TIO* o = out + F * A.o0 + (j - A.o0);
+    const int64_t stride = A.o1 - A.o0;
+    eval_unit<LMAX, V>(x, y, z, k, [&](int f, V v) {
+        const int l = l_of_row(f);
+        V rl;
+#pragma unroll
+        for (int q = 0; q < PPL; ++q) lane<V, PPL>(rl, q) = R[q][l];
+        store_run<TIO, PPL>(o + int64_t(f) * stride, rl * v, PPL);
+    });
+}
+
 // Points per launch: keeps each grid well inside the 32-bit work-item count of a
 // dispatch (a multiple of every lane width, so only the last launch has a tail).
 constexpr int64_t kProjChunk = int64_t(1) << 28;
+
+template <int LMAX, typename TIO, int P>
+static void launch_vec(const ProjArgs<TIO>& A, const SplineGrid& g, dim3 grid, size_t lds, int64_t j0, hipStream_t s)
+{
+    if constexpr (P > 1 && kProjVecSmall<TIO, LMAX>)
+        hipLaunchKernelGGL((proj_vec_kernel<LMAX, TIO, P>), grid, dim3(256), lds, s, A.centers, A.offsets,
+                           A.n_atoms, A.points, A.n_points, A.table, A.tab_ch, A.n_tables, A.table_of_atom, g,
+                           A.out, j0);
+}
 
 template <int LMAX, typename TIO, int P>
 static hipError_t launch_proj_p(const ProjArgs<TIO>& A, hipStream_t s)
@@ -167,10 +278,14 @@ static hipError_t launch_proj_p(const ProjArgs<TIO>& A, hipStream_t s)
     for (int64_t j0 = 0; j0 < A.n_points; j0 += kProjChunk) {
         const int64_t nc = A.n_points - j0 < kProjChunk ? A.n_points - j0 : kProjChunk;
         const dim3 grid = dim3(unsigned((nc + 256 * P - 1) / (256 * P))), block = dim3(256);
+        bool vec = false;
+        if constexpr (P > 1 && kProjVecSmall<TIO, LMAX>) vec = A.n_atoms <= 64;
         if (P == 1 && A.n_atoms <= 64)
             hipLaunchKernelGGL((proj_kernel<LMAX, TIO, P, P == 1>), grid, block, 0, s, A.centers, A.offsets,
                                A.n_atoms, A.points, A.n_points, A.table, A.tab_ch, A.n_tables, A.table_of_atom, g,
                                A.out, j0);
+        else if (vec)
+            launch_vec<LMAX, TIO, P>(A, g, grid, lds, j0, s);
         else
             hipLaunchKernelGGL((proj_kernel<LMAX, TIO, P, false>), grid, block, lds, s, A.centers, A.offsets,
                                A.n_atoms, A.points, A.n_points, A.table, A.tab_ch, A.n_tables, A.table_of_atom, g,

@@ -113,25 +113,30 @@ def test_more_than_64_atoms(dev, orc, dtype):
     assert np.abs(got.astype(LD) - ref).max() <= (1e-13 if dtype == torch.float64 else 5e-6)
 
 
+@pytest.mark.parametrize("lmax", [3, 5])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-def test_large_build_with_odd_atoms(dev, orc, dtype):
+def test_large_build_with_odd_atoms(dev, orc, dtype, lmax):
     """A build of over 2^20 points (the launch that evaluates several adjacent points
-    per lane) whose atoms have odd sizes: lanes straddle atom boundaries and atom
-    blocks start off vector boundaries.  Checked against the oracle on the small
-    atoms and on the first and last 40 points of each large one."""
-    lmax, F = 5, 36
+    per lane; at lmax 3 in proj_vec_kernel, at lmax 5 in proj_kernel) whose atoms
+    have odd sizes: lanes straddle atom boundaries, waves cross several small atoms,
+    and atom blocks start off vector boundaries; the atoms share 4 tables through
+    table_of_atom.  Checked against the oracle on the small atoms and on the first
+    and last 40 points of each large one."""
+    F = (lmax + 1) ** 2
     rng = np.random.default_rng(77)
     sizes = [1, 3, 262145, 5, 262147, 7, 262143, 9, 262149, 2]
     centers = rng.uniform(0.0, 5.0, size=(len(sizes), 3))
     pts = np.concatenate([c + rng.uniform(-1.7, 1.7, size=(k, 3)) for c, k in zip(centers, sizes)])
     offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
-    tables = np.stack([workloads.radial_table(rng, lmax, 300, 3.0) for _ in sizes])
+    shared = np.stack([workloads.radial_table(rng, lmax, 300, 3.0) for _ in range(4)])
+    toa = np.array([(3 * a + 1) % 4 for a in range(len(sizes))])
+    tables = shared[toa]
     if dtype == torch.float32:
         pts = pts.astype(np.float32).astype(np.float64)
         centers = centers.astype(np.float32).astype(np.float64)
     A = workloads.AtomSet(lmax, centers, offsets, pts, tables, 3.0)
-    _say("case: large build with odd atoms,", int(offsets[-1]), "points,", dtype)
-    got = _run(dev, lmax, A, dtype)
+    _say("case: large build with odd atoms,", int(offsets[-1]), "points, lmax", lmax, dtype)
+    got = _run(dev, lmax, A, dtype, tables=shared, table_of_atom=toa)
     segs = []  # (atom, first point, end point)
     for a, k in enumerate(sizes):
         o0 = int(offsets[a])
@@ -292,4 +297,31 @@ def test_inconsistent_offsets_are_skipped_in_bounds(dev, orc):
     ref = orc.projectors(2, A.centers[:1], np.array([0, 40]), A.points[:40], A.tables[:1], A.r_max)
     assert np.abs(got[: F * 40].astype(LD) - ref).max() <= 1e-13
     assert np.all(got[F * 40:] == sentinel)
+    rad.close()
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_inconsistent_offsets_in_a_large_build(dev, dtype):
+    """The same guard on a build of over 2^20 points at lmax 3 (several points per
+    lane, in proj_vec_kernel): with decreasing offsets or an atom ending beyond
+    n_points nothing is written outside out[F * n_points], and whatever is written
+    is finite; with consistent offsets the build writes every value."""
+    rng = np.random.default_rng(31)
+    n, F = (1 << 20) + 4099, 16
+    cen = torch.from_numpy(rng.uniform(0.0, 5.0, size=(3, 3))).to(dev, dtype)
+    pts = torch.from_numpy(rng.uniform(0.0, 5.0, size=(n, 3))).to(dev, dtype)
+    rad = sh.Radial(np.stack([workloads.radial_table(rng, 3, 300, 3.0) for _ in range(3)]), 3.0)
+    fn = sh.sh_projectors if dtype == torch.float64 else sh.sh_projectors_f32
+    sentinel = 12345.0
+    for offs in ([0, 700_001, 300_003, n], [0, 500_000, n + 5000, n + 9000], [9, 2, 1, n], [0, 400_001, 800_003, n]):
+        _say("case: large build, offsets", offs, dtype)
+        big = torch.full((F * n + 4096,), sentinel, dtype=dtype, device=dev)
+        fn(3, cen, torch.tensor(offs, dtype=torch.int64, device=dev), pts, rad, out=big[: F * n])
+        torch.cuda.synchronize()
+        got = big.cpu().numpy()
+        assert np.all(got[F * n:] == sentinel), offs
+        written = got[: F * n] != sentinel
+        assert np.all(np.isfinite(got[: F * n][written])), offs
+        if offs == [0, 400_001, 800_003, n]:
+            assert written.all()
     rad.close()
