@@ -246,15 +246,21 @@ constexpr int64_t kProjVecPoints = int64_t(1) << 20;
 template <typename TIO, int LMAX>
 constexpr size_t kProjCapLds = (sizeof(TIO) == 4 ? LMAX <= 1 : LMAX == 0) ? 0 : 54 * 1024;
 
-// Whether builds with several points per lane over at most 64 atoms run
-// proj_vec_kernel (atoms held in lanes, every knot load of a lane issued before the
-// first spline) instead of proj_kernel (a wave-wide search for the atom, then each
-// point's knots loaded and used in turn).  Measured on 64 x 150k-point builds, two
-// runs each, fractions of 8 TB/s: FP32 lmax 0 / 1 / 2 / 3 / 4 47 / 44-50 / 44 / 53 /
-// 58% -> 53 / 52-56 / 45 / 56-57 / 60%, FP64 lmax 3 57 -> 58-59%; FP32 lmax 5-9 within
-// +-0.5%, FP64 lmax 0-2 and 4-9 0-2% slower.
+// Whether builds with several points per lane run proj_vec_kernel (a window of 64
+// atoms held in lanes, every knot load of a lane issued before the first spline)
+// instead of proj_kernel (a wave-wide search for the atom, then each point's knots
+// loaded and used in turn): kProjVecKernel for builds over at most 64 atoms (the
+// window is all of them), kProjVecWindow for more (the window found by a search).
+// Measured on builds of 9.6M points, two runs each, fractions of 8 TB/s: over 64
+// atoms (150k points each) FP32 lmax 0 / 1 / 2 / 3 / 4 47 / 44-50 / 44 / 53 / 58% ->
+// 53 / 52-56 / 45 / 56-57 / 60%, FP64 lmax 3 57 -> 58-59%, FP32 lmax 5-9 within
+// +-0.5%, FP64 lmax 0-2 and 4-9 0-2% slower; over 256 / 1024 atoms FP32 lmax 0 44 /
+// 36 -> 50 / 39%, lmax 1 39 / 29 -> 41 / 31%, lmax 2 38 / 31 -> 41 / 32%, FP32 lmax
+// 3-4 and FP64 lmax 3 0-4% slower.
 template <typename TIO, int LMAX>
-constexpr bool kProjVecSmall = sizeof(TIO) == 4 ? LMAX <= 4 : LMAX == 3;
+constexpr bool kProjVecKernel = sizeof(TIO) == 4 ? LMAX <= 4 : LMAX == 3;
+template <typename TIO, int LMAX>
+constexpr bool kProjVecWindow = sizeof(TIO) == 4 && LMAX <= 2;
 
 // Lane width of a launch of n points.
 template <typename TIO, int LMAX> constexpr int proj_ppl(int64_t n) { return n >= kProjVecPoints ? kProjPpl<TIO, LMAX> : 1; }

@@ -18,7 +18,7 @@
 // wave-wide search; plain stores; one point per lane, or, for builds of at least
 // kProjVecPoints points, kProjPpl adjacent points per lane evaluated together, with
 // at most 2 resident workgroups per CU (kProjCapLds); those builds run
-// proj_vec_kernel where kProjVecSmall is set (up to 64 atoms).
+// proj_vec_kernel where kProjVecKernel or kProjVecWindow is set.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -157,15 +157,17 @@ __global__ __launch_bounds__(256) void proj_kernel(const TIO* __restrict__ cente
     }
 }
 
-// The launches with several points per lane over at most 64 atoms, for the
-// (dtype, lmax) where kProjVecSmall is set: lane k loads atom k's offsets, centre
-// and table with the points (as the one-point SMALL path does), a ballot gives the
-// wave's atom and the next, and a lane then issues the knot loads of all its
-// points before it evaluates any spline (spline_knots, then spline_from), so the
-// chain per lane is the point loads, one wave of knot loads and the stores.  Each
-// lane's points lie in one of those two atoms unless the wave crosses more than
-// one atom boundary; such lanes, and lanes that straddle a boundary, take their
-// points one by one.  The same arithmetic as proj_kernel, so the same bits.
+// The launches with several points per lane, for the (dtype, lmax) where
+// kProjVecKernel (at most 64 atoms) or kProjVecWindow (more) is set: lane k loads
+// the offsets, centre and table of atom a0 + k with the points (a0 = 0 for at most
+// 64 atoms, as the one-point SMALL path does; otherwise the wave's atom, from one
+// wave-wide search), a ballot gives the wave's
+// atom and the next, and a lane then issues the knot loads of all its points before
+// it evaluates any spline (spline_knots, then spline_from), so the chain per lane is
+// the point loads, one wave of knot loads and the stores.  Each lane's points lie
+// in one of those two atoms unless the wave crosses more than one atom boundary;
+// such lanes, and lanes that straddle a boundary, take their points one by one.
+// The same arithmetic as proj_kernel, so the same bits.
 template <int LMAX, typename TIO, int PPL>
 __global__ __launch_bounds__(256) void proj_vec_kernel(const TIO* __restrict__ centers,
                                                        const int64_t* __restrict__ offsets, int n_atoms,
@@ -190,8 +192,14 @@ __global__ __launch_bounds__(256) void proj_vec_kernel(const TIO* __restrict__ c
         r.t = t < 0 ? 0 : (t >= n_tables ? n_tables - 1 : t);
         return r;
     };
+    int a0 = 0;  // first atom of the window held in the lanes
+    if (n_atoms > 64) {
+        a0 = wave_search(offsets, n_atoms, w0);
+        a0 = a0 < 0 ? 0 : a0;
+    }
+    const int nw = n_atoms - a0 < 64 ? n_atoms - a0 : 64;
     AtomRef mine{};
-    if (wl < n_atoms) mine = load_atom(wl);
+    if (wl < nw) mine = load_atom(a0 + wl);
     const int64_t j = w0 + wl * PPL;
     double px[PPL], py[PPL], pz[PPL];
 #pragma unroll
@@ -206,11 +214,11 @@ __global__ __launch_bounds__(256) void proj_vec_kernel(const TIO* __restrict__ c
                        {lane_value(mine.c[0], a), lane_value(mine.c[1], a), lane_value(mine.c[2], a)},
                        lane_value(mine.t, a)};
     };
-    const int aw = __popcll(__ballot(wl < n_atoms && mine.o0 <= w0)) - 1;
-    AtomRef A0, A1;  // atoms aw and aw + 1 (o0 = o1 = -1 if there is none)
+    const int aw = __popcll(__ballot(wl < nw && mine.o0 <= w0)) - 1;  // in the window
+    AtomRef A0, A1;  // atoms a0 + aw and a0 + aw + 1 (o0 = o1 = -1 if there is none)
     A0.o0 = A0.o1 = A1.o0 = A1.o1 = -1;
     if (aw >= 0) A0 = atom_at(aw);
-    if (aw + 1 < n_atoms) A1 = atom_at(aw + 1);
+    if (aw + 1 < nw) A1 = atom_at(aw + 1);
     if (j >= n_points) return;
     const bool in0 = A0.o0 >= 0 && A0.o0 <= j && j + PPL <= A0.o1 && A0.o1 <= n_points;
     const bool in1 = A1.o0 >= 0 && A1.o0 <= j && j + PPL <= A1.o1 && A1.o1 <= n_points;
@@ -264,7 +272,7 @@ constexpr int64_t kProjChunk = int64_t(1) << 28;
 template <int LMAX, typename TIO, int P>
 static void launch_vec(const ProjArgs<TIO>& A, const SplineGrid& g, dim3 grid, size_t lds, int64_t j0, hipStream_t s)
 {
-    if constexpr (P > 1 && kProjVecSmall<TIO, LMAX>)
+    if constexpr (P > 1 && (kProjVecKernel<TIO, LMAX> || kProjVecWindow<TIO, LMAX>))
         hipLaunchKernelGGL((proj_vec_kernel<LMAX, TIO, P>), grid, dim3(256), lds, s, A.centers, A.offsets,
                            A.n_atoms, A.points, A.n_points, A.table, A.tab_ch, A.n_tables, A.table_of_atom, g,
                            A.out, j0);
@@ -278,8 +286,7 @@ static hipError_t launch_proj_p(const ProjArgs<TIO>& A, hipStream_t s)
     for (int64_t j0 = 0; j0 < A.n_points; j0 += kProjChunk) {
         const int64_t nc = A.n_points - j0 < kProjChunk ? A.n_points - j0 : kProjChunk;
         const dim3 grid = dim3(unsigned((nc + 256 * P - 1) / (256 * P))), block = dim3(256);
-        bool vec = false;
-        if constexpr (P > 1 && kProjVecSmall<TIO, LMAX>) vec = A.n_atoms <= 64;
+        const bool vec = P > 1 && (A.n_atoms <= 64 ? kProjVecKernel<TIO, LMAX> : kProjVecWindow<TIO, LMAX>);
         if (P == 1 && A.n_atoms <= 64)
             hipLaunchKernelGGL((proj_kernel<LMAX, TIO, P, P == 1>), grid, block, 0, s, A.centers, A.offsets,
                                A.n_atoms, A.points, A.n_points, A.table, A.tab_ch, A.n_tables, A.table_of_atom, g,

@@ -153,6 +153,52 @@ def test_large_build_with_odd_atoms(dev, orc, dtype, lmax):
         assert np.abs(block.astype(LD) - want).max() <= tol, (a, j0)
 
 
+@pytest.mark.parametrize("lmax", [2, 5])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_large_build_with_many_atoms(dev, orc, dtype, lmax):
+    """A build of over 2^20 points over 380 atoms (more than a wave's 64 lanes: in
+    FP32 at lmax 2 proj_vec_kernel holds a window of 64 atoms found by a search,
+    otherwise proj_kernel searches per wave), with a run of 80 atoms of 1-3 points,
+    so some waves cross more atoms than the window holds.  Checked against the oracle on the
+    small atoms and on the first and last 40 points of each large one, and bit for
+    bit against some atoms built alone."""
+    F = (lmax + 1) ** 2
+    rng = np.random.default_rng(79)
+    sizes = list(rng.integers(3500, 3700, size=150)) + list(rng.integers(1, 4, size=80)) \
+        + list(rng.integers(3500, 3700, size=150))
+    assert sum(sizes) > 1 << 20
+    centers = rng.uniform(0.0, 12.0, size=(len(sizes), 3))
+    pts = np.concatenate([c + rng.uniform(-1.7, 1.7, size=(k, 3)) for c, k in zip(centers, sizes)])
+    offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    shared = np.stack([workloads.radial_table(rng, lmax, 300, 3.0) for _ in range(5)])
+    toa = np.array([(7 * a + 2) % 5 for a in range(len(sizes))])
+    tables = shared[toa]
+    if dtype == torch.float32:
+        pts = pts.astype(np.float32).astype(np.float64)
+        centers = centers.astype(np.float32).astype(np.float64)
+    A = workloads.AtomSet(lmax, centers, offsets, pts, tables, 3.0)
+    _say("case: large build with", len(sizes), "atoms,", int(offsets[-1]), "points, lmax", lmax, dtype)
+    got = _run(dev, lmax, A, dtype, tables=shared, table_of_atom=toa)
+    segs = []  # (atom, first point, end point)
+    for a, k in enumerate(sizes):
+        o0 = int(offsets[a])
+        segs += [(a, o0, o0 + k)] if k < 100 else [(a, o0, o0 + 40), (a, o0 + k - 40, o0 + k)]
+    sub_pts = np.concatenate([pts[j0:j1] for _, j0, j1 in segs])
+    sub_off = np.concatenate([[0], np.cumsum([j1 - j0 for _, j0, j1 in segs])]).astype(np.int64)
+    ref = orc.projectors(lmax, centers[[a for a, _, _ in segs]], sub_off, sub_pts,
+                         tables[[a for a, _, _ in segs]], 3.0)
+    tol = 1e-13 if dtype == torch.float64 else 5e-6
+    for s, (a, j0, j1) in enumerate(segs):
+        o0, na = int(offsets[a]), sizes[a]
+        block = got[F * o0:F * (o0 + na)].reshape(F, na)[:, j0 - o0:j1 - o0]
+        want = ref[F * sub_off[s]:F * sub_off[s + 1]].reshape(F, j1 - j0)
+        assert np.abs(block.astype(LD) - want).max() <= tol, (a, j0)
+    for a in (0, 149, 150, 190, 229, 230, 379):
+        one = workloads.AtomSet(lmax, centers[a:a + 1], np.array([0, sizes[a]], dtype=np.int64),
+                                pts[offsets[a]:offsets[a + 1]], tables[a:a + 1], 3.0)
+        assert np.array_equal(got[F * offsets[a]:F * offsets[a + 1]], _run(dev, lmax, one, dtype)), a
+
+
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_handle_with_more_channels_than_the_build(dev, orc, dtype):
     """A radial handle of 10 channels (lmax 9) used for builds at every lmax below
