@@ -231,11 +231,13 @@ __device__ __forceinline__ void proj_points(const double (&px)[PPL], const doubl
 // launch too small to fill the GPU waits for; launches below kProjVecPoints points
 // keep one point per lane.  The widths, and the LDS reservation below, were chosen
 // per (dtype, lmax) on 64 x 150k-point builds from tables of lmax + 1 channels:
-// FP64 four points at lmax 1-2, two elsewhere (lmax 0: 45% of 8 TB/s against 42%
-// with four and the reservation; lmax 3: 56% against 53-54%; lmax 1-2: 46 / 51%
-// against 44 / 50% with two; lmax >= 4: two, +35% at lmax 6 over one, four 7-10%
-// slower); FP32 four (+10-21% at lmax 3-9 over one; two or eight no faster).
-template <typename TIO, int LMAX> constexpr int kProjPpl = sizeof(TIO) == 4 ? 4 : (LMAX == 1 || LMAX == 2 ? 4 : 2);
+// FP64 four points at lmax 1, two elsewhere (lmax 0: 45% of 8 TB/s against 42%
+// with four and the reservation; lmax 3: 56% against 53-54%; lmax 1: 46% against
+// 44% with two; lmax 2, where proj_vec_kernel runs: 51.4-51.6% with two against
+// 47.3-47.7% with four in proj_kernel; lmax >= 4: two, +35% at lmax 6 over one,
+// four 7-10% slower); FP32 four (+10-21% at lmax 3-9 over one; two or eight no
+// faster).
+template <typename TIO, int LMAX> constexpr int kProjPpl = sizeof(TIO) == 4 ? 4 : (LMAX == 1 ? 4 : 2);
 constexpr int64_t kProjVecPoints = int64_t(1) << 20;
 
 // LDS reserved (not used) by the launches with several points per lane: at most 2
@@ -253,12 +255,13 @@ constexpr size_t kProjCapLds = (sizeof(TIO) == 4 ? LMAX <= 1 : LMAX == 0) ? 0 : 
 // window is all of them), kProjVecWindow for more (the window found by a search).
 // Measured on builds of 9.6M points, two runs each, fractions of 8 TB/s: over 64
 // atoms (150k points each) FP32 lmax 0 / 1 / 2 / 3 / 4 47 / 44-50 / 44 / 53 / 58% ->
-// 53 / 52-56 / 45 / 56-57 / 60%, FP64 lmax 3 57 -> 58-59%, FP32 lmax 5-9 within
-// +-0.5%, FP64 lmax 0-2 and 4-9 0-2% slower; over 256 / 1024 atoms FP32 lmax 0 44 /
+// 53 / 52-56 / 45 / 56-57 / 60%, FP64 lmax 2 47-48 (four points per lane) -> 51-52%
+// (two), FP64 lmax 3 57 -> 58-59%, FP32 lmax 5-9 within +-0.5%, FP64 lmax 0-1 and
+// 4-9 0-2% slower; over 256 / 1024 atoms FP32 lmax 0 44 /
 // 36 -> 50 / 39%, lmax 1 39 / 29 -> 41 / 31%, lmax 2 38 / 31 -> 41 / 32%, FP32 lmax
 // 3-4 and FP64 lmax 3 0-4% slower.
 template <typename TIO, int LMAX>
-constexpr bool kProjVecKernel = sizeof(TIO) == 4 ? LMAX <= 4 : LMAX == 3;
+constexpr bool kProjVecKernel = sizeof(TIO) == 4 ? LMAX <= 4 : (LMAX == 2 || LMAX == 3);
 template <typename TIO, int LMAX>
 constexpr bool kProjVecWindow = sizeof(TIO) == 4 && LMAX <= 2;
 

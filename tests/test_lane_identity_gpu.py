@@ -94,10 +94,10 @@ def test_other_kernels_vector_and_single_lanes(dev):
 @pytest.mark.parametrize("dt", [torch.float64, torch.float32])
 def test_projector_build_vector_and_single_lanes(dev, dt, lmax):
     """Nine atoms of 120,001 to 120,009 points: together they take the launch with
-    several adjacent points per lane (more than 2^20 points: 4 FP64 points at
-    lmax 2, 2 at lmax 0, 3 and 5, 4 FP32 points; the odd sizes make lanes straddle
-    atom boundaries; proj_vec_kernel for FP32 at lmax <= 3 and FP64 at lmax 3,
-    proj_kernel otherwise), each alone the one-point launch.  Every atom's block is
+    several adjacent points per lane (more than 2^20 points: 2 FP64 points, 4 FP32
+    points; the odd sizes make lanes straddle atom boundaries; proj_vec_kernel for
+    FP32 at lmax <= 3 and FP64 at lmax 2 and 3, proj_kernel otherwise), each alone
+    the one-point launch.  Every atom's block is
     the same bit for bit."""
     rng = np.random.default_rng(21)
     sizes = [120_001 + k for k in range(9)]
