@@ -219,10 +219,11 @@ def bench_store_probes(xyz, out, head, steps):
     """The headline kernel's store pattern without its arithmetic, and plain fills,
     over the same buffers: `rows100` loads each lane's two points and writes 100
     rows of 16 bytes in the headline kernel's launch shape (256 lanes, XCD-ordered
-    tiles, at most 2 workgroups per CU); `rows10` the same with 10 rows; `fill` one
-    16-byte store per lane over the whole output (plain, and with the sc1 cache
-    policy bit).  `frac_of_store_pattern` is the headline kernel's rate over
-    rows100's."""
+    tiles, one resident workgroup per CU); `rows100_2wg` the same with at most 2
+    workgroups per CU (the shape of the kernels below lmax 8); `rows10` 10 rows, 2
+    workgroups per CU; `fill` one 16-byte store per lane over the whole output
+    (plain, and with the sc1 cache policy bit).  `frac_of_store_pattern` is the
+    headline kernel's rate over rows100's."""
     import torch
     P = store_probe_lib()
     n = xyz.shape[0]
@@ -233,7 +234,9 @@ def bench_store_probes(xyz, out, head, steps):
             raise RuntimeError(f"store probe rejected its arguments ({rc})")
 
     res = {}
-    cases = (("rows100", n * (24 + 800), lambda: chk(P.shp_rows(xyz.data_ptr(), out.data_ptr(), n, n, 100, 1, 0, 1, 0, st))),
+    cases = (("rows100", n * (24 + 800), lambda: chk(P.shp_rows(xyz.data_ptr(), out.data_ptr(), n, n, 100, 1, 0, 2, 0, st))),
+             ("rows100_2wg", n * (24 + 800),
+              lambda: chk(P.shp_rows(xyz.data_ptr(), out.data_ptr(), n, n, 100, 1, 0, 1, 0, st))),
              ("rows10", n * (24 + 80), lambda: chk(P.shp_rows(xyz.data_ptr(), out.data_ptr(), n, n, 10, 1, 0, 1, 0, st))),
              ("fill", n * 800, lambda: chk(P.shp_fill(out.data_ptr(), n * 800, 0, st))),
              ("fill_sc1", n * 800, lambda: chk(P.shp_fill(out.data_ptr(), n * 800, 4, st))))

@@ -38,6 +38,14 @@ constexpr int64_t kFwdVecPoints = int64_t(1) << 18;
 // than a third of the CU's 160 KiB, so at most 2 workgroups are resident per CU.
 constexpr size_t kCapLds = 54 * 1024;
 
+// The same for the real-harmonic kernel: FP64 at lmax >= 8 reserves more than half
+// of the LDS, one resident workgroup (4 waves) per CU, fewer row streams at once.
+// Measured on 2^26 points, fractions of 8 TB/s over five runs: FP64 lmax 9 67.8% ->
+// 68.1-68.4%, lmax 8 68.0% -> 68.1-68.2%; lmax 7 and below and FP32 at every lmax
+// equal or slower (FP64 lmax 2 74 -> 70%, FP32 lmax 2 74 -> 63%).
+template <typename TIO, int LMAX>
+constexpr size_t kFwdCapLds = sizeof(TIO) == 8 && LMAX >= 8 ? 84 * 1024 : kCapLds;
+
 // Input pointers of a launch that starts at point c0.
 template <In MODE, typename TIO>
 struct Inputs {
@@ -55,7 +63,8 @@ static hipError_t launch_one(Inputs<MODE, TIO> in, TIO* out, int64_t n, int64_t 
 {
     const int64_t nvec = n / PPL;
     const unsigned grid = unsigned((nvec + kFwdBlock - 1) / kFwdBlock);
-    hipLaunchKernelGGL((fwd_kernel<LMAX, TIO, PPL, MODE>), dim3(grid), dim3(kFwdBlock), PPL > 1 ? kCapLds : 0, s,
+    constexpr size_t lds = PPL > 1 ? kFwdCapLds<TIO, LMAX> : 0;
+    hipLaunchKernelGGL((fwd_kernel<LMAX, TIO, PPL, MODE>), dim3(grid), dim3(kFwdBlock), lds, s,
                        in.a, out, uint32_t(n), ld, in.b);
     return hipGetLastError();
 }

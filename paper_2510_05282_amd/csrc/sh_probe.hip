@@ -20,8 +20,9 @@
 //              k >= 2 (split 1 only)  8 << (k - 1) contiguous ranges of tiles,
 //                 2^(k-1) per XCD, taken in turn by its workgroups (smaller write
 //                 windows per range, more ranges).
-//            `cap` reserves LDS to allow at most 2 workgroups per CU (as the
-//            forward kernel does); `mode` picks the store instruction: 0 global
+//            `cap` reserves LDS to allow at most 2 workgroups per CU (cap 1, as the
+//            forward kernel does below lmax 8) or 1 (cap 2, as it does in FP64 at
+//            lmax 8 and 9); `mode` picks the store instruction: 0 global
 //            store, 1.. buffer stores with cache-policy bits (see kAux).
 //  shp_fwd_split  the lmax 9 FP64 forward kernel with its rows split the same
 //            way: a workgroup evaluates only the harmonics of its row range.
@@ -38,7 +39,9 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 // cache-policy bits of the buffer-store variants: sc0 = 1, nt = 2, sc1 = 16
 constexpr int kAux[] = {0, 0, 2, 1, 16, 17, 18, 3, 19};
 constexpr int kModes = int(sizeof(kAux) / sizeof(kAux[0]));
-constexpr size_t kCapLds = 54 * 1024;
+constexpr size_t kCapLds = 54 * 1024;   // cap 1: at most 2 resident workgroups per CU
+constexpr size_t kCapLds1 = 84 * 1024;  // cap 2: 1
+__host__ inline size_t cap_lds(int cap) { return cap == 2 ? kCapLds1 : (cap ? kCapLds : 0); }
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(void* base, uint32_t bytes)
 {
@@ -212,7 +215,7 @@ int shp_rows(const double* xyz, double* out, int64_t n, int64_t ld, int rows, in
     const uint32_t tiles = uint32_t(n / 512);
     const dim3 grid(tiles * unsigned(split)), block(256);
     const hipError_t e = with_mode(mode, [&](auto mc) {
-        hipLaunchKernelGGL(rows_kernel<decltype(mc)::value>, grid, block, cap ? kCapLds : 0, s, xyz, out, tiles, ld,
+        hipLaunchKernelGGL(rows_kernel<decltype(mc)::value>, grid, block, cap_lds(cap), s, xyz, out, tiles, ld,
                            rows, split, order);
         return hipGetLastError();
     });
@@ -228,7 +231,7 @@ int shp_fwd_split(const double* xyz, double* out, int64_t n, int64_t ld, int spl
         return 1;
     const uint32_t tiles = uint32_t(n / 512);
     const dim3 grid(tiles * unsigned(split)), block(256);
-    const size_t lds = cap ? kCapLds : 0;
+    const size_t lds = cap_lds(cap);
     switch (split) {
     case 1: hipLaunchKernelGGL(fwd_split_kernel<1>, grid, block, lds, s, xyz, out, tiles, ld, order); break;
     case 2: hipLaunchKernelGGL(fwd_split_kernel<2>, grid, block, lds, s, xyz, out, tiles, ld, order); break;
