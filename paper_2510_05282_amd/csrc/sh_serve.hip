@@ -160,6 +160,13 @@ static hipError_t launch_mixed(int64_t tiles, const ServeInline& in, const Serve
     return hipGetLastError();
 }
 
+// Lane width of the vector-lane serving launches: the projector build's, except FP64
+// at lmax 2, which keeps four points per lane here (the build moved to two in
+// proj_vec_kernel; serve_kernel, which loads each point's knots in turn, took 116 us
+// per lmax 2 FP64 launch with two against 87 us with four, closed-loop kernel trace).
+template <typename TIO, int LMAX>
+constexpr int kServePpl = sizeof(TIO) == 8 && LMAX == 2 ? 4 : kProjPpl<TIO, LMAX>;
+
 template <int LMAX, typename TIO>
 static void launch_group_l(int ppl, int64_t tiles, const ServeInline& in, const ServeDesc* descs,
                            const int64_t* tile0, int n, hipStream_t s, hipEvent_t done)
@@ -168,7 +175,7 @@ static void launch_group_l(int ppl, int64_t tiles, const ServeInline& in, const 
     if (ppl == 1)
         hipExtLaunchKernelGGL((serve_kernel<LMAX, TIO, 1>), grid, block, 0, s, nullptr, done, 0, in, descs, tile0, n);
     else
-        hipExtLaunchKernelGGL((serve_kernel<LMAX, TIO, kProjPpl<TIO, LMAX>>), grid, block,
+        hipExtLaunchKernelGGL((serve_kernel<LMAX, TIO, kServePpl<TIO, LMAX>>), grid, block,
                               uint32_t(kProjCapLds<TIO, LMAX>), s, nullptr, done, 0, in, descs, tile0, n);
 }
 
@@ -181,11 +188,11 @@ static void launch_group_l(int ppl, int64_t tiles, const ServeInline& in, const 
 // unchanged within its spread (2^19: in between).
 constexpr int64_t kServeVecPoints = int64_t(1) << 18;
 
-// Lane width of a group of n points of one (dtype, lmax): 1 or kProjPpl.
+// Lane width of a group of n points of one (dtype, lmax): 1 or kServePpl.
 template <typename TIO, int... L>
 static int vec_ppl_of(int lmax, std::integer_sequence<int, L...>)
 {
-    constexpr int w[] = {kProjPpl<TIO, L>...};
+    constexpr int w[] = {kServePpl<TIO, L>...};
     return w[lmax];
 }
 static int group_ppl(int dtype, int lmax, int64_t n)
@@ -195,7 +202,7 @@ static int group_ppl(int dtype, int lmax, int64_t n)
                            : vec_ppl_of<double>(lmax, std::make_integer_sequence<int, SH_LMAX + 1>{});
 }
 
-// ppl is 1 or kProjPpl<TIO, lmax>; descs null: the n <= kInlineItems descriptors
+// ppl is 1 or kServePpl<TIO, lmax>; descs null: the n <= kInlineItems descriptors
 // of `in`, else n descriptors at descs and their first tiles at tile0 (device)
 template <typename TIO>
 static hipError_t launch_group(int lmax, int ppl, int64_t tiles, const ServeInline& in, const ServeDesc* descs,

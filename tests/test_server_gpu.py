@@ -244,7 +244,7 @@ def test_alone_and_in_a_vector_group_bitwise(dev, lmax):
     time (each its own launch, one point per lane), then all at once behind a large
     request that holds the only stream slot, so that they form one batch whose
     (dtype, lmax) groups exceed 2^18 points and take the launch with several
-    adjacent points per lane (2 FP64 points, 4 FP32).  Each
+    adjacent points per lane (4 FP64 points at lmax 2, 2 at lmax 5, 4 FP32).  Each
     result is identical bit for bit in both runs and to sh_projectors of its atom
     alone."""
     rng = np.random.default_rng(14)
