@@ -234,9 +234,9 @@ __device__ __forceinline__ void proj_points(const double (&px)[PPL], const doubl
 // FP64 four points at lmax 1, two elsewhere (lmax 0: 45% of 8 TB/s against 42%
 // with four and the reservation; lmax 3: 56% against 53-54%; lmax 1: 46% against
 // 44% with two; lmax 2, where proj_vec_kernel runs: 51.4-51.6% with two against
-// 47.3-47.7% with four in proj_kernel; lmax >= 4: two, +35% at lmax 6 over one,
-// four 7-10% slower); FP32 four (+10-21% at lmax 3-9 over one; two or eight no
-// faster).
+// 47.3-47.7% with four in proj_kernel, while serving keeps four there, kServePpl;
+// lmax >= 4: two, +35% at lmax 6 over one, four 7-10% slower); FP32 four (+10-21% at
+// lmax 3-9 over one; two or eight no faster).
 template <typename TIO, int LMAX> constexpr int kProjPpl = sizeof(TIO) == 4 ? 4 : (LMAX == 1 ? 4 : 2);
 constexpr int64_t kProjVecPoints = int64_t(1) << 20;
 
