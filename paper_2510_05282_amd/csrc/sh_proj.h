@@ -245,17 +245,17 @@ constexpr int64_t kProjVecPoints = int64_t(1) << 20;
 // smaller window (as for the forward kernel).  Measured on the same builds: +1-13%
 // at FP64 lmax 1-9 and FP32 lmax >= 2; FP64 lmax 0 and FP32 lmax 0-1 run faster
 // without it (the FP64 lmax 0 launch with two points per lane: 45% against 34%).
+// At lmax 9, and FP64 lmax 8, more than half of the LDS: one resident workgroup per
+// CU.  Measured on 64 x 150k-point builds, two runs each: FP64 lmax 9 64.1-64.3% ->
+// 65.4%, FP32 60.3-60.6% -> 61.2-61.3% of 8 TB/s, FP64 lmax 8 63.5-63.7% ->
+// 64.0-64.2%; FP64 lmax 7, FP32 lmax 7-8 and every lmax up to 6 slower (FP32 lmax 7
+// 60.5 -> 56.9%, lmax 6 62 -> 58%); serving (its vector-lane groups), two passes
+// each: closed loop 111.7-112.2k -> 113.4-114.3k req/s, Poisson p50 and p99 equal or
+// lower.
 template <typename TIO, int LMAX>
-constexpr size_t kProjCapLds = (sizeof(TIO) == 4 ? LMAX <= 1 : LMAX == 0) ? 0 : 54 * 1024;
-
-// The same for the projector builds (not the serving groups): at lmax 9, and FP64
-// lmax 8, more than half of the LDS, one resident workgroup per CU.  Measured on 64 x
-// 150k-point builds, two runs each: FP64 lmax 9 64.1-64.3% -> 65.4%, FP32 60.3-60.6%
-// -> 61.2-61.3% of 8 TB/s, FP64 lmax 8 63.5-63.7% -> 64.0-64.2%; FP64 lmax 7, FP32
-// lmax 7-8 and every lmax up to 6 slower (FP32 lmax 7 60.5 -> 56.9%, lmax 6 62 -> 58%).
-template <typename TIO, int LMAX>
-constexpr size_t kProjBuildCapLds =
-    (LMAX == 9 || (sizeof(TIO) == 8 && LMAX == 8)) ? 84 * 1024 : kProjCapLds<TIO, LMAX>;
+constexpr size_t kProjCapLds = (LMAX == 9 || (sizeof(TIO) == 8 && LMAX == 8))
+                                   ? 84 * 1024
+                                   : ((sizeof(TIO) == 4 ? LMAX <= 1 : LMAX == 0) ? 0 : 54 * 1024);
 
 // Whether builds with several points per lane run proj_vec_kernel (a window of 64
 // atoms held in lanes, every knot load of a lane issued before the first spline)

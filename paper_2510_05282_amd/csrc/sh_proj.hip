@@ -282,7 +282,7 @@ template <int LMAX, typename TIO, int P>
 static hipError_t launch_proj_p(const ProjArgs<TIO>& A, hipStream_t s)
 {
     const SplineGrid g{A.n_r, A.h, 1.0 / A.h, A.r_max, A.h * A.h / 6.0};
-    const size_t lds = P > 1 ? kProjBuildCapLds<TIO, LMAX> : 0;
+    const size_t lds = P > 1 ? kProjCapLds<TIO, LMAX> : 0;
     for (int64_t j0 = 0; j0 < A.n_points; j0 += kProjChunk) {
         const int64_t nc = A.n_points - j0 < kProjChunk ? A.n_points - j0 : kProjChunk;
         const dim3 grid = dim3(unsigned((nc + 256 * P - 1) / (256 * P))), block = dim3(256);
